@@ -1,0 +1,176 @@
+/*
+ * FP64 CPU oracle for the batched HJCD-IK solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant with the GPU library: it is a plain, slow,
+ * step-by-step FP64 statement of what the method computes, written from the
+ * paper (arXiv 2510.07514):
+ *
+ *   - forward kinematics and geometric Jacobian      Sec. II, eq. (fk), (jacobian)
+ *   - task residual and quaternion error             Sec. II, eq. (task_residual), (quat_diff)
+ *   - CCD position step                              Sec. II-A, eq. (vec_proj), (theta_proj)
+ *   - orientation angle-axis step                    Sec. III, eq. (angle_axis), (ori_update)
+ *   - PO-CCD greedy sweep, gamma test, perturbation  Sec. IV-A, Alg. PO-CCD
+ *   - top-K + noisy replication                      Sec. IV, Alg. HJCD-IK
+ *   - PJ-IK: weighted LM, trust region, line search,
+ *     dogleg, single-coordinate step, perturbation   Sec. IV-B, eq. (normal-eqs),
+ *                                                    (line-search), (dogleg), (single-coord),
+ *                                                    Alg. PJ-IK
+ *   - sphere collision filter and final argmin       Sec. IV-C, Alg. HJCD-IK
+ *   - Philox4x32-10 (Salmon et al., SC'11) and Box-Muller normals for the
+ *     random draws the paper leaves unspecified.
+ *
+ * Where the paper is silent or garbled the oracle follows the readings listed
+ * in the design notes of the repository (sign conventions, annealing, line
+ * search order, dogleg root, single-coordinate step length, constants).
+ *
+ * All arrays are host memory owned by the caller.  Angles in rad, lengths in m.
+ * Functions return 0 on success and a negative value on invalid input.
+ */
+#ifndef HJCD_ORACLE_H
+#define HJCD_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_MAX_DOF 32
+
+typedef struct {
+    int32_t dof;                 /* 1..OR_MAX_DOF */
+    int32_t convention;          /* 0 = modified DH (Craig), 1 = standard DH */
+    const double* a;             /* [dof] */
+    const double* d;             /* [dof] */
+    const double* alpha;         /* [dof] */
+    const double* offset;        /* [dof] */
+    const double* q_min;         /* [dof] */
+    const double* q_max;         /* [dof] */
+    const double* tool;          /* [16] row-major 4x4 */
+    int32_t n_spheres;
+    const int32_t* sphere_link;  /* [n_spheres] link index 0..dof */
+    const double* sphere_xyzr;   /* [n_spheres*4] centre in link frame, radius */
+    int32_t min_link_gap;        /* self pairs need |la-lb| >= gap; 0 = no self test */
+} or_robot;
+
+typedef struct {
+    int32_t n_spheres;
+    const double* spheres;       /* [n*4] x y z r */
+    int32_t n_boxes;
+    const double* boxes;         /* [n*6] cx cy cz hx hy hz */
+} or_scene;
+
+typedef struct {
+    int32_t cd_sweeps, polish_iters;
+    double eps_cd, nu_cd, gamma, delta0, delta_decay, delta_min, proj_eps;
+    double lam, lambda_gn, trust_R, ls_beta;
+    int32_t ls_A, weight_mode;
+    double eps_pol, ups_pol, sigma, mu;
+    int32_t resample_K, resample_B, top_k;
+    double succ_pos, succ_ori;
+    uint64_t rng_seed;
+} or_params;
+
+/* Per-seed record of one stage run (PO-CCD or PJ-IK). */
+typedef struct {
+    int32_t iters_run;      /* iterations whose update step executed */
+    int32_t frozen_at;      /* iteration index at which the exit test fired, -1 = never */
+    int32_t n_perturb;      /* perturbations taken */
+    int32_t n_trials;       /* PJ-IK: trial cost evaluations (line search + dogleg) */
+    int32_t n_dogleg;       /* PJ-IK: dogleg steps computed */
+    int32_t n_single;       /* PJ-IK: single-coordinate steps computed */
+} or_stage_stats;
+
+/* ---- kinematics ---------------------------------------------------------- */
+
+/* FK at theta[dof].  Outputs (any may be NULL):
+ *   p_ee[3], R_ee[9] (row-major), quat[4] (w x y z, w >= 0),
+ *   joint_P[dof*3], joint_z[dof*3] (origin and unit axis of each joint),
+ *   link_T[(dof+1)*12] (rows 0..2 of each link frame, row-major 3x4),
+ *   J[6*dof] (row-major 6 x dof geometric Jacobian). */
+int or_fk(const or_robot* rb, const double* theta, double* p_ee, double* R_ee, double* quat,
+          double* joint_P, double* joint_z, double* link_T, double* J);
+
+/* Rotation matrix -> unit quaternion (w x y z), Shepperd's method, w >= 0. */
+void or_quat_from_R(const double* R, double* q);
+
+/* Residual of a pose against a target (p_t[3], q_t[4] w x y z):
+ * out[0..2] = r_p = p_t - p_ee, out[3..5] = omega, out[6] = phi,
+ * out[7..9] = unit error axis a_hat (0 if phi = 0), out[10] = cost
+ * 0.5 (|r_p|^2 + |omega|^2). */
+void or_residual(const double* p_t, const double* q_t, const double* p_ee, const double* R_ee,
+                 double* out);
+
+/* ---- random numbers ------------------------------------------------------- */
+
+void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out);
+
+/* Standard normal draws for one seed: z[dof] keyed by (seed, target key, stage, iter). */
+void or_normals(uint64_t rng_seed, uint32_t seed_idx, uint32_t target_key, uint32_t stage,
+                uint32_t iter, int dof, double* z);
+
+/* Uniform seed in the joint limits keyed the same way (stage 0). */
+void or_uniform_seed(const or_robot* rb, uint64_t rng_seed, uint32_t seed_idx,
+                     uint32_t target_key, double* theta);
+
+/* ---- stages (one seed) ---------------------------------------------------- */
+
+/* PO-CCD on one seed.  theta[dof] in/out.  target[7] = px py pz qw qx qy qz.
+ * traj (nullable) receives (cd_sweeps+1) rows of (dof + 2) values:
+ *   row 0 = start, row k+1 = after iteration k: theta, |r_p|, phi.
+ * margin (nullable) receives cd_sweeps values: the smallest decision margin
+ * (m or rad) met in each iteration, +inf when the iteration made no
+ * consequential decision (see or_cd comments). */
+int or_cd(const or_robot* rb, const double* target, const or_params* pr, uint32_t seed_idx,
+          uint32_t target_key, double* theta, double* traj, double* margin, or_stage_stats* st);
+
+/* PJ-IK on one seed; same conventions with polish_iters iterations. */
+int or_polish(const or_robot* rb, const double* target, const or_params* pr, uint32_t seed_idx,
+              uint32_t target_key, double* theta, double* traj, double* margin,
+              or_stage_stats* st);
+
+/* Inspection of one PO-CCD iteration k at theta: per-joint clipped position
+ * steps dp[dof], orientation steps dor[dof] and their scores sp[dof]
+ * (|r_p|^2 after moving that joint alone) and so[dof] (|omega|^2). */
+int or_cd_candidates(const or_robot* rb, const double* target, const or_params* pr,
+                     const double* theta, int32_t k, double* dp, double* dor, double* sp,
+                     double* so);
+
+/* Inspection of the PJ-IK steps at theta: lm[dof] (unclipped LM step),
+ * gd[dof], gn[dof] (dogleg gradient and Gauss-Newton steps), dogleg[dof]
+ * (blended step), single[dof] (single-coordinate step) and *single_idx. */
+int or_pjik_steps(const or_robot* rb, const double* target, const or_params* pr,
+                  const double* theta, double* lm, double* gd, double* gn, double* dogleg,
+                  double* single, int32_t* single_idx);
+
+/* Collision of one configuration: returns via flag (1 = collides) and
+ * min_signed_dist (smallest distance - radii over every tested pair; +inf
+ * when nothing was tested). */
+int or_collide(const or_robot* rb, const or_scene* sc, const double* theta, int32_t* flag,
+               double* min_signed_dist);
+
+/* Final per-target selection over m seeds: stable order by (flag, cost,
+ * index); order[k] receives the first k seed indices (-1 past m). */
+int or_select(int32_t m, const int32_t* flag, const double* cost, int32_t k, int32_t* order);
+
+/* ---- whole pipeline --------------------------------------------------------
+ * T targets (targets[T*7]), CSR seed offsets[T+1], seeds (nullable, AoS
+ * [S*dof] doubles; NULL = uniform Philox seeds), target_keys (nullable, [T];
+ * NULL = target index).  Per-seed outputs (nullable, indexed by final seed
+ * slot; with resampling the final slots are t*B' + j, B' = floor(B/K)*K):
+ *   q_seed[S'*dof], errp_seed[S'], erro_seed[S'], cost_seed[S'], flag_seed[S']
+ * Per-target outputs: q_out[T*k*dof], err_p[T*k], err_o[T*k], flag_out[T*k]
+ * (255 for empty slots), n_free[T], solved[T] (1 if a returned seed is
+ * collision free within succ_pos / succ_ori).  nthreads 0 = all cores. */
+int or_solve(const or_robot* rb, const or_scene* sc, int32_t T, const double* targets,
+             const int64_t* offsets, const double* seeds, const uint32_t* target_keys,
+             const or_params* pr, double* q_seed, double* errp_seed, double* erro_seed,
+             double* cost_seed, int32_t* flag_seed, double* q_out, double* err_p, double* err_o,
+             int32_t* flag_out, int32_t* n_free, int32_t* solved, int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
