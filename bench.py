@@ -1,0 +1,194 @@
+"""Benchmark of the batched HJCD-IK solve on one MI355X.
+
+One step = one hjcd_solve over the whole batch (seed init, PO-CCD, PJ-IK,
+collision filter, top-k selection) with every input resident in HBM.
+Workload: Panda-like 7-DoF chain, 1,000 targets x 1,024 seeds, 60 link
+spheres, 32 obstacle spheres, top-8 (the batched configuration).
+
+Prints one JSON line.  `value` = collision-free solves per second at 1 mm /
+1 deg (targets with a returned collision-free seed within tolerance, per
+second of wall time).  `roofline` prices the fused PO-CCD + PJ-IK kernel's
+algorithmic FP32 flops (per-unit counts x executed units, counted live by
+the kernel) against the MI355X FP32 vector peak; `cpu_baseline` times the
+FP64 oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD public spec)
+PEAK_HBM_GBS = 8000.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic FP32 flops of the fused solve kernel per executed unit.
+# Counted from the kernel's arithmetic (add/mul = 1, fma = 2, each
+# transcendental sin / cos / atan2 / sqrt / log / div = 1); see the design doc.
+# ---------------------------------------------------------------------------
+def fk_flops(n, modified=True, tool_rot=False):
+    return (57 if modified else 51) * n + 18 + (45 if tool_rot else 0)
+
+
+RESIDUAL = 64 + 3  # residual + cost
+
+
+def unit_flops(n, modified=True, tool_rot=False):
+    fk = fk_flops(n, modified, tool_rot)
+    return dict(
+        cd_iter=fk + RESIDUAL + 6 + 116 * n + 178,
+        pol_iter=fk + RESIDUAL + 669 + 110 * n,
+        pol_trial=fk + RESIDUAL + 2 * n + 1,
+        pol_dogleg=94 * n + 200,
+        pol_single=36 * n + 2,
+        perturb=9 * n,
+        seed=5 * n + 2 * (fk + RESIDUAL + 1),  # seed init + final FK of both stages
+    )
+
+
+def algorithmic_flops(n, st, modified=True, tool_rot=False):
+    u = unit_flops(n, modified, tool_rot)
+    return (st["cd_iters"] * u["cd_iter"] + st["pol_iters"] * u["pol_iter"]
+            + st["pol_trials"] * u["pol_trial"] + st["pol_dogleg"] * u["pol_dogleg"]
+            + st["pol_single"] * u["pol_single"]
+            + (st["cd_perturb"] + st["pol_perturb"]) * u["perturb"] + st["seeds"] * u["seed"])
+
+
+def cpu_baseline(batch, n_targets):
+    """FP64 oracle on the first n_targets targets of the batch (all their
+    seeds, uniform Philox seeds like the GPU run), all host cores."""
+    import oracle as O
+    rob = batch.robots[0]
+    sub_q = batch.q_star[:n_targets]
+    tg = O.targets_from_qstar(rob, sub_q).astype(np.float64)
+    M = int(batch.seed_offsets[1] - batch.seed_offsets[0])
+    offs = np.arange(n_targets + 1, dtype=np.int64) * M
+    cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    out = O.solve(rob, batch.scene, tg, offs, batch.params, seeds=None, nthreads=cores)
+    dt = time.perf_counter() - t0
+    solved = int(out["solved"].sum())
+    return {"value": solved / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_targets} of {batch.T} targets x {M} seeds, FP64, {dt:.1f} s wall",
+            "solved": solved, "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--targets", type=int, default=1000)
+    ap.add_argument("--seeds", type=int, default=1024)
+    ap.add_argument("--cpu-targets", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_07514_amd import hjcd as H
+    from paper_2510_07514_amd import workload as W
+
+    batch = W.config_batched(T=args.targets, M=args.seeds, host_seeds=False)
+    rob = batch.robots[0]
+    n, T, k = rob.dof, batch.T, batch.params["top_k"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    ctx = H.hjcd_ctx_create(0)
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, batch.scene.spheres, batch.scene.boxes)
+    with torch.cuda.stream(stream):
+        # targets = FK(q*) by the library's own FK kernel
+        qs = torch.as_tensor(np.ascontiguousarray(np.asarray(batch.q_star, np.float32).T)).to(dev)
+        pose = torch.zeros(7, T, device=dev)
+        H.hjcd_fk(ctx, rb, qs, pose, None, stream=stream)
+        targets = pose.contiguous()
+        q_out = torch.zeros(T * k, n, device=dev)
+        ep = torch.zeros(T * k, device=dev)
+        eo = torch.zeros(T * k, device=dev)
+        fl = torch.zeros(T * k, dtype=torch.uint8, device=dev)
+        nf = torch.zeros(T, dtype=torch.int32, device=dev)
+        sv = torch.zeros(T, dtype=torch.uint8, device=dev)
+    p = H.params_from_dict(batch.params, collect_stats=True)
+
+    def step():
+        H.hjcd_solve(ctx, [rb], sc, targets, batch.seed_offsets, p, q_out, ep, eo, fl, nf, sv,
+                     stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    kern_ms, step_ms, solved = [], [], []
+    agg = None
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        step()
+        st = H.hjcd_get_stats(ctx)  # waits for this step's last event on `stream`
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        kern_ms.append(st["ms_solve_kernel"])
+        if agg is None:
+            agg = {kk: 0 for kk in st}
+        for kk, v in st.items():
+            agg[kk] += v
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    n_solved = int(sv.sum().item())
+    ms_per_step = wall * 1e3 / args.steps
+    value = n_solved / (ms_per_step / 1e3)
+    steps = args.steps
+    per_step = {kk: v / steps for kk, v in agg.items()}
+    flops = algorithmic_flops(n, per_step)
+    kavg = float(np.mean(kern_ms))
+    achieved = flops / (kavg * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "k_solve (fused PO-CCD + PJ-IK)", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
+    line = {
+        "metric": "collision-free IK solves/s at 1mm/1deg",
+        "value": round(value, 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched_panda_{T}x{args.seeds}", "targets": T,
+                   "seeds_per_target": args.seeds, "dof": n, "link_spheres": int(rob.sphere_link.shape[0]),
+                   "obstacle_spheres": int(batch.scene.spheres.shape[0]), "top_k": k,
+                   "cd_sweeps": batch.params["cd_sweeps"], "polish_iters": batch.params["polish_iters"]},
+        "solved_targets": n_solved,
+        "success_rate": round(n_solved / T, 4),
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3)},
+        "stage_ms": {kk: round(per_step[kk], 4) for kk in
+                     ("ms_solve_kernel", "ms_collide", "ms_select", "ms_total")},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_targets, T))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,7 +51,7 @@ class _Params(C.Structure):
     _fields_ = [("cd_sweeps", C.c_int32), ("polish_iters", C.c_int32),
                 ("eps_cd", C.c_double), ("nu_cd", C.c_double), ("gamma", C.c_double),
                 ("delta0", C.c_double), ("delta_decay", C.c_double), ("delta_min", C.c_double),
-                ("proj_eps", C.c_double), ("lam", C.c_double), ("lambda_gn", C.c_double),
+                ("proj_eps", C.c_double), ("tie_eps", C.c_double), ("lam", C.c_double), ("lambda_gn", C.c_double),
                 ("trust_R", C.c_double), ("ls_beta", C.c_double),
                 ("ls_A", C.c_int32), ("weight_mode", C.c_int32),
                 ("eps_pol", C.c_double), ("ups_pol", C.c_double), ("sigma", C.c_double),
@@ -141,7 +141,7 @@ class SceneHandle:
 
 def params(p: dict) -> _Params:
     return _Params(int(p["cd_sweeps"]), int(p["polish_iters"]), p["eps_cd"], p["nu_cd"],
-                   p["gamma"], p["delta0"], p["delta_decay"], p["delta_min"], p["proj_eps"],
+                   p["gamma"], p["delta0"], p["delta_decay"], p["delta_min"], p["proj_eps"], p["tie_eps"],
                    p["lam"], p["lambda_gn"], p["trust_R"], p["ls_beta"], int(p["ls_A"]),
                    int(p["weight_mode"]), p["eps_pol"], p["ups_pol"], p["sigma"], p["mu"],
                    int(p["resample_K"]), int(p["resample_B"]), int(p["top_k"]),

@@ -450,17 +450,23 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
         double dp[OR_MAX_DOF], dor[OR_MAX_DOF], sp[OR_MAX_DOF], so[OR_MAX_DOF];
         cd_candidates(rb, tg, p, th, k, f, r, dp, dor, sp, so, mg, harm);
 
-        // Greedy picks (ties -> lower joint index).
-        int jp = 0, jo = 0;
-        for (int j = 1; j < n; ++j) {
-            if (sp[j] < sp[jp]) jp = j;
-            if (so[j] < so[jo]) jo = j;
+        // Greedy picks: the lowest joint whose score (|r_p| for position, |omega|
+        // for orientation) lies within tie_eps of the best one.
+        double dmin = kInf, omin = kInf;
+        for (int j = 0; j < n; ++j) {
+            dmin = std::min(dmin, std::sqrt(sp[j]));
+            omin = std::min(omin, std::sqrt(so[j]));
+        }
+        int jp = -1, jo = -1;
+        for (int j = 0; j < n; ++j) {
+            if (jp < 0 && std::sqrt(sp[j]) <= dmin + p.tie_eps) jp = j;
+            if (jo < 0 && std::sqrt(so[j]) <= omin + p.tie_eps) jo = j;
         }
         for (int j = 0; j < n; ++j) {
-            if (j != jp && std::fabs(dp[jp]) + std::fabs(dp[j]) > harm)
-                mg.add(std::fabs(std::sqrt(sp[j]) - std::sqrt(sp[jp])));
-            if (j != jo && std::fabs(dor[jo]) + std::fabs(dor[j]) > harm)
-                mg.add(std::fabs(std::sqrt(so[j]) - std::sqrt(so[jo])));
+            if (std::fabs(dp[jp]) + std::fabs(dp[j]) > harm)
+                mg.add(std::fabs(std::sqrt(sp[j]) - dmin - p.tie_eps));
+            if (std::fabs(dor[jo]) + std::fabs(dor[j]) > harm)
+                mg.add(std::fabs(std::sqrt(so[j]) - omin - p.tie_eps));
         }
 
         // theta_hat: both moves if they act on different joints, otherwise the
@@ -543,7 +549,8 @@ double vnorm(int n, const double* x) {
 // 1/beta^A]; the first alpha whose clipped iterate lowers the cost wins.
 // Returns true and updates theta on success.
 bool line_search(const Robot& rb, const Target& tg, const or_params& p, double* th,
-                 const double* step, double c0, Margin& mg, or_stage_stats& st, double harm) {
+                 const double* step, double c0, Margin& mg, or_stage_stats& st, double harm,
+                 double* alpha_taken) {
     const int n = rb.n;
     double alpha = 1.0;
     for (int i = 0; i <= p.ls_A; ++i) {
@@ -558,6 +565,7 @@ bool line_search(const Robot& rb, const Target& tg, const or_params& p, double* 
         if (smax > harm) mg.add(std::fabs(std::sqrt(2.0 * r.cost) - std::sqrt(2.0 * c0)));
         if (r.cost < c0) {
             std::memcpy(th, tt, sizeof(double) * n);
+            if (alpha_taken) *alpha_taken = alpha;
             return true;
         }
         alpha /= p.ls_beta;
@@ -700,6 +708,74 @@ int single_step(const Lin& L, const or_params& p, double* step, Margin& mg) {
 }
 
 // ---------------------------------------------------------------------------
+// Conditioning of a PJ-IK step (test instrumentation, not part of the
+// method): how far the step moves when J and e carry single-precision-sized
+// errors.  Near singular configurations the damped systems amplify such
+// errors up to 1/lambda; an iteration whose step moves by more than
+// kSensTol is treated like a near-tie decision (margin 0).
+// ---------------------------------------------------------------------------
+const double kSensTol = 2e-6;
+enum StepKind { STEP_LM = 0, STEP_DOGLEG = 1, STEP_SINGLE = 2, STEP_PERTURB = 3 };
+
+Lin perturbed(const Lin& L, const or_params& p, uint64_t key) {
+    Lin P = L;
+    uint64_t x = key * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+    auto sgn = [&x]() {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        return (x >> 11) & 1 ? 1.0 : -1.0;
+    };
+    const int n = L.n;
+    for (int i = 0; i < 6 * n; ++i) P.J[i] = L.J[i] * (1.0 + 2.4e-7 * sgn()) + 1e-7 * sgn();
+    for (int i = 0; i < 6; ++i) P.e[i] = L.e[i] + 3e-7 * sgn();
+    for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += P.J[i * n + j] * P.J[i * n + j];
+        P.w[i] = (p.weight_mode == 0) ? 1.0 / std::max(std::sqrt(s), 1e-6) : 1.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < 6; ++i) s += P.J[i * n + j] * P.J[i * n + j];
+        P.Dg[j] = s;
+    }
+    return P;
+}
+
+void step_of_kind(const Lin& L, const or_params& p, int kind, double alpha, int is, double* out) {
+    const int n = L.n;
+    if (kind == STEP_LM) {
+        lm_step(L, p, out);
+        for (int j = 0; j < n; ++j) out[j] = alpha * clip(out[j], -p.trust_R, p.trust_R);
+    } else if (kind == STEP_DOGLEG) {
+        double gd[OR_MAX_DOF], gn[OR_MAX_DOF];
+        dogleg_step(L, p, out, gd, gn);
+    } else {
+        double gw = 0.0, h = 0.0;
+        for (int i = 0; i < 6; ++i) {
+            gw += L.J[i * n + is] * L.w[i] * L.w[i] * L.e[i];
+            h += L.J[i * n + is] * L.w[i] * L.w[i] * L.J[i * n + is];
+        }
+        for (int j = 0; j < n; ++j) out[j] = 0.0;
+        out[is] = alpha * (h > 0.0 ? clip(gw / h, -p.trust_R, p.trust_R) : 0.0);
+    }
+}
+
+double step_sensitivity(const Lin& L, const or_params& p, int kind, double alpha, int is, int it) {
+    if (kind == STEP_PERTURB) return 0.0;
+    const int n = L.n;
+    double base[OR_MAX_DOF], alt[OR_MAX_DOF];
+    step_of_kind(L, p, kind, alpha, is, base);
+    double worst = 0.0;
+    for (int rep = 0; rep < 4; ++rep) {
+        Lin P = perturbed(L, p, (uint64_t)(it * 8 + rep + 1));
+        step_of_kind(P, p, kind, alpha, is, alt);
+        for (int j = 0; j < n; ++j) worst = std::max(worst, std::fabs(alt[j] - base[j]));
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
 // PJ-IK on one seed (Alg. PJ-IK, Sec. IV-B)
 // ---------------------------------------------------------------------------
 void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, uint32_t tkey,
@@ -733,9 +809,13 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
         double dth[OR_MAX_DOF];
         lm_step(L, p, dth);
         for (int j = 0; j < n; ++j) dth[j] = clip(dth[j], -R, R);
-        bool ok = line_search(rb, tg, p, th, dth, c0, mg, st, harm);
+        double alpha = 1.0;
+        int kind = STEP_LM, is = 0;
+        bool ok = line_search(rb, tg, p, th, dth, c0, mg, st, harm, &alpha);
         if (!ok) {
             // Dogleg fallback, one trial.
+            kind = STEP_DOGLEG;
+            alpha = 1.0;
             st.n_dogleg++;
             double step[OR_MAX_DOF], gd[OR_MAX_DOF], gn[OR_MAX_DOF];
             dogleg_step(L, p, step, gd, gn);
@@ -756,13 +836,16 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             // Single-coordinate fallback with the same line search.
             st.n_single++;
             double step[OR_MAX_DOF];
-            single_step(L, p, step, mg);
-            ok = line_search(rb, tg, p, th, step, c0, mg, st, harm);
+            kind = STEP_SINGLE;
+            is = single_step(L, p, step, mg);
+            ok = line_search(rb, tg, p, th, step, c0, mg, st, harm, &alpha);
         }
         if (!ok) {
+            kind = STEP_PERTURB;
             perturb(rb, p, m, tkey, ST_POLISH, (uint32_t)it, th);
             st.n_perturb++;
         }
+        if (step_sensitivity(L, p, kind, alpha, is, it) > kSensTol) mg.add(0.0);
         st.iters_run++;
         if (margin) margin[it] = mg.v;
     }

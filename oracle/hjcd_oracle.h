@@ -64,7 +64,7 @@ typedef struct {
 
 typedef struct {
     int32_t cd_sweeps, polish_iters;
-    double eps_cd, nu_cd, gamma, delta0, delta_decay, delta_min, proj_eps;
+    double eps_cd, nu_cd, gamma, delta0, delta_decay, delta_min, proj_eps, tie_eps;
     double lam, lambda_gn, trust_R, ls_beta;
     int32_t ls_A, weight_mode;
     double eps_pol, ups_pol, sigma, mu;

@@ -1,0 +1,67 @@
+"""Build libhjcd.so for gfx950 in-tree (``python -m paper_2510_07514_amd.build``).
+
+Every HIP translation unit is compiled by hipcc for --offload-arch=gfx950 in
+parallel (the per-seed solve kernel once per joint-count bucket), then linked
+into ``paper_2510_07514_amd/libhjcd.so``.  Packed-FP32 instructions are
+disabled for all device code.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libhjcd.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+
+ARCH = "gfx950"
+NM_BUCKETS = (8, 16, 24, 32)
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", CSRC, "-I", INCLUDE]
+
+
+def _units():
+    units = [("hjcd_kernels.o", "hjcd_kernels.hip", []),
+             ("hjcd_api.o", "hjcd_api.cpp", ["-x", "hip"])]
+    for nm in NM_BUCKETS:
+        units.append((f"hjcd_solve_nm{nm}.o", "hjcd_solve_inst.hip", [f"-DHJCD_NM={nm}"]))
+    return units
+
+
+def _compile(unit, verbose):
+    obj, src, extra = unit
+    cmd = [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src} {extra}:\n{r.stdout}\n{r.stderr}")
+    return obj
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every unit and link libhjcd.so; returns the library path."""
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    jobs = jobs or min(len(units), max(1, min(os.cpu_count() or 4, 8)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda u: _compile(u, verbose), units))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
+          [os.path.join(BUILD, o) for o in objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,961 @@
+// Device-side math of the batched HJCD-IK solve for gfx950 (CDNA4).
+//
+// One seed per lane.  The joint vector, the joint frames and the 6 x 6 LM
+// system live in VGPRs; robot and obstacle tables are read with wave-uniform
+// indices so they come through the scalar data cache (s_load); nothing of a
+// seed's state touches memory between its first read and its last write.
+// Arrays are sized by the compile-time bucket NM >= n (n is wave-uniform and
+// every per-joint loop is unrolled to NM with a uniform `j < n` guard).
+//
+// Citations refer to arXiv 2510.07514.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hjcd_launch.hpp"
+#include "hjcd_tables.hpp"
+
+namespace hjcd {
+
+// ----------------------------------------------------------------------------
+// small vector / quaternion helpers
+// ----------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ V3 mk(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(float s, V3 a) { return mk(s * a.x, s * a.y, s * a.z); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+    return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// a + s b
+__device__ __forceinline__ V3 axpy(float s, V3 b, V3 a) {
+    return mk(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y), fmaf(s, b.z, a.z));
+}
+
+struct Quat {
+    float w, x, y, z;
+};
+
+// Hamilton product (a0, a)(b0, b) = (a0 b0 - a.b, a0 b + b0 a + a x b)
+__device__ __forceinline__ Quat qmul(Quat a, Quat b) {
+    Quat r;
+    r.w = a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z;
+    r.x = a.w * b.x + b.w * a.x + a.y * b.z - a.z * b.y;
+    r.y = a.w * b.y + b.w * a.y + a.z * b.x - a.x * b.z;
+    r.z = a.w * b.z + b.w * a.z + a.x * b.y - a.y * b.x;
+    return r;
+}
+
+// Rigid frame: rotation columns X, Y, Z and origin p.
+struct Frame {
+    V3 X, Y, Z, p;
+};
+
+__device__ __forceinline__ Frame identity_frame() {
+    return Frame{mk(1, 0, 0), mk(0, 1, 0), mk(0, 0, 1), mk(0, 0, 0)};
+}
+
+__device__ __forceinline__ float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
+
+// ----------------------------------------------------------------------------
+// Forward kinematics (eq. fk): joint origins P_i and axes Z_i (STORE), and the
+// end-effector frame.  Column updates of R * Rx(alpha) * Rz(theta):
+//   modified DH: p += R (a, -d sin alpha, d cos alpha); R <- R Rx(alpha) Rz(theta);
+//                joint i = frame i
+//   standard DH: joint i = frame i-1; p += a (R Rz(theta)).X + d R.Z;
+//                R <- R Rz(theta) Rx(alpha)
+// ----------------------------------------------------------------------------
+template <int NM, bool STORE>
+__device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n, const float* th,
+                                         V3* P, V3* Z, Frame& ee) {
+    Frame T = identity_frame();
+    if (rb->conv == 0) {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                float s, c;
+                sincosf(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
+                V3 Yb = axpy(sa, T.Z, ca * T.Y);
+                V3 Zb = axpy(-sa, T.Y, ca * T.Z);
+                V3 Xn = axpy(s, Yb, c * T.X);
+                V3 Yn = axpy(-s, T.X, c * Yb);
+                T.X = Xn;
+                T.Y = Yn;
+                T.Z = Zb;
+                if (STORE) {
+                    P[i] = T.p;
+                    Z[i] = T.Z;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                if (STORE) {
+                    P[i] = T.p;
+                    Z[i] = T.Z;
+                }
+                float s, c;
+                sincosf(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                V3 Xb = axpy(s, T.Y, c * T.X);
+                V3 Yb = axpy(-s, T.X, c * T.Y);
+                T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
+                V3 Yn = axpy(sa, T.Z, ca * Yb);
+                V3 Zn = axpy(-sa, Yb, ca * T.Z);
+                T.X = Xb;
+                T.Y = Yn;
+                T.Z = Zn;
+            }
+        }
+    }
+    // end effector = T_0n * tool
+    const float* tl = rb->tool;
+    ee.p = axpy(tl[11], T.Z, axpy(tl[7], T.Y, axpy(tl[3], T.X, T.p)));
+    if (rb->tool_rot) {
+        ee.X = axpy(tl[8], T.Z, axpy(tl[4], T.Y, tl[0] * T.X));
+        ee.Y = axpy(tl[9], T.Z, axpy(tl[5], T.Y, tl[1] * T.X));
+        ee.Z = axpy(tl[10], T.Z, axpy(tl[6], T.Y, tl[2] * T.X));
+    } else {
+        ee.X = T.X;
+        ee.Y = T.Y;
+        ee.Z = T.Z;
+    }
+}
+
+// One link-frame step of the chain (used by the collision pass, which needs
+// every link frame).  Advances T from frame i-1 to frame i.
+__device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int i, float theta,
+                                           Frame& T) {
+    float s, c;
+    sincosf(theta + rb->off[i], &s, &c);
+    const float ca = rb->ca[i], sa = rb->sa[i];
+    if (rb->conv == 0) {
+        T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
+        V3 Yb = axpy(sa, T.Z, ca * T.Y);
+        V3 Zb = axpy(-sa, T.Y, ca * T.Z);
+        V3 Xn = axpy(s, Yb, c * T.X);
+        V3 Yn = axpy(-s, T.X, c * Yb);
+        T.X = Xn;
+        T.Y = Yn;
+        T.Z = Zb;
+    } else {
+        V3 Xb = axpy(s, T.Y, c * T.X);
+        V3 Yb = axpy(-s, T.X, c * T.Y);
+        T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
+        V3 Yn = axpy(sa, T.Z, ca * Yb);
+        V3 Zn = axpy(-sa, Yb, ca * T.Z);
+        T.X = Xb;
+        T.Y = Yn;
+        T.Z = Zn;
+    }
+}
+
+// Rotation -> unit quaternion, Shepperd's method (largest of trace and the
+// diagonal decides the divisor), w >= 0.
+__device__ __forceinline__ Quat quat_of(const Frame& F) {
+    const float R00 = F.X.x, R10 = F.X.y, R20 = F.X.z;
+    const float R01 = F.Y.x, R11 = F.Y.y, R21 = F.Y.z;
+    const float R02 = F.Z.x, R12 = F.Z.y, R22 = F.Z.z;
+    const float tr = R00 + R11 + R22;
+    const bool c0 = tr >= R00 && tr >= R11 && tr >= R22;
+    const bool c1 = !c0 && R00 >= R11 && R00 >= R22;
+    const bool c2 = !c0 && !c1 && R11 >= R22;
+    const float big = c0 ? 1.f + tr : c1 ? 1.f + R00 - R11 - R22 : c2 ? 1.f - R00 + R11 - R22
+                                                                       : 1.f - R00 - R11 + R22;
+    const float r = sqrtf(big);
+    const float qb = 0.5f * r;
+    const float k = 0.5f / r;
+    const float d21 = (R21 - R12) * k, d02 = (R02 - R20) * k, d10 = (R10 - R01) * k;
+    const float s01 = (R01 + R10) * k, s02 = (R02 + R20) * k, s12 = (R12 + R21) * k;
+    Quat q;
+    q.w = c0 ? qb : c1 ? d21 : c2 ? d02 : d10;
+    q.x = c0 ? d21 : c1 ? qb : c2 ? s01 : s02;
+    q.y = c0 ? d02 : c1 ? s01 : c2 ? qb : s12;
+    q.z = c0 ? d10 : c1 ? s02 : c2 ? s12 : qb;
+    if (q.w < 0.f) {
+        q.w = -q.w;
+        q.x = -q.x;
+        q.y = -q.y;
+        q.z = -q.z;
+    }
+    return q;
+}
+
+// Task residual (eq. task_residual, eq. quat_diff): r_p = P_t - P_ee and the
+// error quaternion q_err = q_t (x) q_e^-1 taken with w >= 0 (short rotation);
+// phi = 2 atan2(|v|, w) in [0, pi].
+struct Err {
+    V3 rp;
+    Quat q;     // canonical error quaternion
+    float s;    // |v|
+    float phi;  // rotation angle
+    float ep2;  // |r_p|^2
+};
+
+struct Target {
+    V3 p;
+    Quat q;
+};
+
+__device__ __forceinline__ Err residual(const Frame& ee, const Target& tg) {
+    Err e;
+    e.rp = tg.p - ee.p;
+    e.ep2 = dot(e.rp, e.rp);
+    Quat qe = quat_of(ee);
+    qe.x = -qe.x;
+    qe.y = -qe.y;
+    qe.z = -qe.z;
+    Quat q = qmul(tg.q, qe);
+    if (q.w < 0.f) {
+        q.w = -q.w;
+        q.x = -q.x;
+        q.y = -q.y;
+        q.z = -q.z;
+    }
+    e.q = q;
+    e.s = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
+    e.phi = 2.f * atan2f(e.s, q.w);
+    return e;
+}
+
+// omega of eq. (quat_diff): (phi / |v|) v, or 2 v / w when |v| vanishes.
+__device__ __forceinline__ V3 omega_of(const Err& e) {
+    const float f = e.s > 1e-20f ? e.phi / e.s : 2.f / e.q.w;
+    return mk(f * e.q.x, f * e.q.y, f * e.q.z);
+}
+
+__device__ __forceinline__ float cost_of(const Err& e) { return 0.5f * (e.ep2 + e.phi * e.phi); }
+
+__device__ __forceinline__ Target load_target(const float* __restrict__ tg, int64_t T, int64_t t) {
+    Target g;
+    g.p = mk(tg[t], tg[T + t], tg[2 * T + t]);
+    float w = tg[3 * T + t], x = tg[4 * T + t], y = tg[5 * T + t], z = tg[6 * T + t];
+    float inv = 1.f / sqrtf(w * w + x * x + y * y + z * z);
+    g.q = Quat{w * inv, x * inv, y * inv, z * inv};
+    return g;
+}
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the draws built on it
+// ----------------------------------------------------------------------------
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox(U4 ctr, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * ctr.a, hi0 = __umulhi(0xD2511F53u, ctr.a);
+        const uint32_t lo1 = 0xCD9E8D57u * ctr.c, hi1 = __umulhi(0xCD9E8D57u, ctr.c);
+        ctr = U4{hi1 ^ ctr.b ^ k0, lo1, hi0 ^ ctr.d ^ k1, lo0};
+    }
+    return ctr;
+}
+
+enum { STAGE_INIT = 0, STAGE_CD = 1, STAGE_RESAMPLE = 2, STAGE_POLISH = 3 };
+
+// Uniform in (0, 1) from the top 24 bits: exact in single precision.
+__device__ __forceinline__ float uni24(uint32_t x) {
+    return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
+}
+
+__device__ __forceinline__ U4 draw(uint64_t seed, uint32_t m, uint32_t tkey, uint32_t stage,
+                                   uint32_t iter, uint32_t block) {
+    return philox(U4{m, tkey, (stage << 24) | (iter & 0xFFFFFFu), block}, (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// theta <- clip(theta + mu + sigma z), z ~ N(0, I) by Box-Muller: joint j takes
+// word pair (2p, 2p+1), p = (j % 4) / 2, of block j / 4; cos for even j, sin
+// for odd j.
+template <int NM>
+__device__ __forceinline__ void perturb(const DevRobot* __restrict__ rb, int n, float* th,
+                                        uint64_t seed, uint32_t m, uint32_t tkey, uint32_t stage,
+                                        uint32_t iter, float mu, float sigma) {
+#pragma unroll
+    for (int b = 0; b < (NM + 3) / 4; ++b) {
+        if (4 * b < n) {
+            U4 x = draw(seed, m, tkey, stage, iter, (uint32_t)b);
+            const uint32_t w[4] = {x.a, x.b, x.c, x.d};
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const float rad = sqrtf(-2.f * logf(uni24(w[2 * p])));
+                float sn, cs;
+                sincospif(2.f * uni24(w[2 * p + 1]), &sn, &cs);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int j = 4 * b + 2 * p + h;
+                    if (j < NM && j < n) {
+                        const float z = h == 0 ? rad * cs : rad * sn;
+                        th[j] = clampf(th[j] + mu + sigma * z, rb->lo[j], rb->hi[j]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NM>
+__device__ __forceinline__ void uniform_seed(const DevRobot* __restrict__ rb, int n, float* th,
+                                             uint64_t seed, uint32_t m, uint32_t tkey) {
+#pragma unroll
+    for (int b = 0; b < (NM + 3) / 4; ++b) {
+        if (4 * b < n) {
+            U4 x = draw(seed, m, tkey, STAGE_INIT, 0, (uint32_t)b);
+            const uint32_t w[4] = {x.a, x.b, x.c, x.d};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int j = 4 * b + h;
+                if (j < NM && j < n) th[j] = fmaf(rb->hi[j] - rb->lo[j], uni24(w[h]), rb->lo[j]);
+            }
+        }
+    }
+}
+
+// Rodrigues rotation of w about unit axis z by the angle whose half-angle
+// cosine / sine are (ch, sh).
+__device__ __forceinline__ V3 rot_half(V3 z, float ch, float sh, V3 w) {
+    const float s = 2.f * sh * ch;
+    const float omc = 2.f * sh * sh;  // 1 - cos
+    return axpy(omc * dot(z, w), z, axpy(s, cross(z, w), axpy(-omc, w, w)));
+}
+
+// q (x) conj(q_z(angle)) with q_z(angle) = (ch, sh z)
+__device__ __forceinline__ Quat qmul_conj_axis(Quat q, V3 z, float ch, float sh) {
+    Quat r;
+    const float vz = q.x * z.x + q.y * z.y + q.z * z.z;
+    r.w = q.w * ch + sh * vz;
+    // ch v - w sh z - sh (v x z)
+    const V3 v = mk(q.x, q.y, q.z);
+    const V3 vxz = cross(v, z);
+    r.x = ch * v.x - q.w * sh * z.x - sh * vxz.x;
+    r.y = ch * v.y - q.w * sh * z.y - sh * vxz.y;
+    r.z = ch * v.z - q.w * sh * z.z - sh * vxz.z;
+    return r;
+}
+
+// ----------------------------------------------------------------------------
+// Per-lane counters of executed work (summed per wave, then atomically)
+// ----------------------------------------------------------------------------
+struct Counters {
+    uint32_t cd_iters = 0, cd_perturb = 0, pol_iters = 0, pol_trials = 0, pol_dogleg = 0,
+             pol_single = 0, pol_perturb = 0, coll_coarse = 0, coll_fine = 0;
+};
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* __restrict__ out,
+                                               bool enabled) {
+    if (!enabled) return;
+    const uint32_t v[9] = {c.cd_iters, c.cd_perturb, c.pol_iters, c.pol_trials, c.pol_dogleg,
+                           c.pol_single, c.pol_perturb, c.coll_coarse, c.coll_fine};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t s = wave_sum(v[i]);
+        if ((threadIdx.x & 63) == 0 && s) atomicAdd(out + i, (unsigned long long)s);
+    }
+}
+
+__device__ __forceinline__ bool wave_all(bool p) {
+    return __ballot(!p) == 0ull;
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0ull; }
+
+// ----------------------------------------------------------------------------
+// Parameters as the kernels read them (KernelParams of hjcd_launch.hpp)
+// ----------------------------------------------------------------------------
+using KParams = KernelParams;
+
+// ----------------------------------------------------------------------------
+// Trajectory row: theta, |r_p|, phi of every seed, [rows][n+2][S].
+template <int NM>
+__device__ __forceinline__ void write_traj(float* __restrict__ traj, int n, int64_t S, int64_t s,
+                                           int row, const float* th, float ep, float phi) {
+    if (!traj) return;
+    float* base = traj + (int64_t)row * (n + 2) * S + s;
+#pragma unroll
+    for (int j = 0; j < NM; ++j)
+        if (j < n) base[(int64_t)j * S] = th[j];
+    base[(int64_t)n * S] = ep;
+    base[(int64_t)(n + 1) * S] = phi;
+}
+
+// ----------------------------------------------------------------------------
+// PO-CCD (Alg. PO-CCD, Sec. III, Sec. IV-A) on one seed.  `live` is false
+// for padding lanes; they run the uniform control flow with no effect.
+// ----------------------------------------------------------------------------
+template <int NM>
+__device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
+                       uint32_t m, uint32_t tkey, float* th, bool live, Counters& cnt,
+                       float* __restrict__ traj, int64_t S, int64_t s, Err& out_err) {
+    bool frozen = !live;
+    float last_ep = 0.f, last_phi = 0.f;
+    V3 P[NM], Z[NM];
+    float delta = kp.delta0;
+    for (int k = 0; k < kp.cd_sweeps; ++k) {
+        if (wave_all(frozen) && !traj) break;
+        if (!frozen) {
+            Frame ee;
+            fk_chain<NM, true>(rb, n, th, P, Z, ee);
+            const Err e = residual(ee, tg);
+            last_ep = sqrtf(e.ep2);
+            last_phi = e.phi;
+            // exit test on the configuration the previous iteration produced
+            if (e.ep2 < kp.eps_cd2 && e.phi < kp.nu_cd) frozen = true;
+            if (live) write_traj<NM>(traj, n, S, s, k, th, last_ep, last_phi);
+            if (!frozen) {
+                ++cnt.cd_iters;
+                const float dk = fmaxf(kp.delta_min, delta);
+                // half-angle of the unclamped orientation move |delta(k) phi|
+                float shu, chu;
+                sincosf(0.5f * dk * e.phi, &shu, &chu);
+                // --- per-joint candidates ---------------------------------
+                // scores in |r_p| (m) and phi (rad) units, kept per joint for the
+                // tie-tolerant pick below
+                float sP[NM], dP[NM], sO[NM], dO[NM];
+                float dmin = 3.4e38f, omin = 3.4e38f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    sP[j] = 3.4e38f;
+                    sO[j] = 3.4e38f;
+                    dP[j] = 0.f;
+                    dO[j] = 0.f;
+                    if (j < n) {
+                        const V3 z = Z[j];
+                        const V3 u = ee.p - P[j];
+                        const V3 v = tg.p - P[j];
+                        const float uz = dot(u, z), vz = dot(v, z);
+                        const V3 up = axpy(-uz, z, u);
+                        const V3 vp = axpy(-vz, z, v);
+                        const float du2 = dot(up, up), dv2 = dot(vp, vp);
+                        const bool valid = du2 >= kp.proj_eps2 && dv2 >= kp.proj_eps2;
+                        // eq. (vec_proj) / (theta_proj), signed about z
+                        const float C = dot(up, vp);
+                        const float Sg = dot(z, cross(up, vp));
+                        const float d = valid ? atan2f(Sg, C) : 0.f;
+                        const float lo = rb->lo[j], hi = rb->hi[j];
+                        const float tj = th[j];
+                        const bool clp = (tj + d > hi) || (tj + d < lo);
+                        const float dp = clp ? clampf(tj + d, lo, hi) - tj : d;
+                        float sp;
+                        const float az = vz - uz;
+                        if (!valid) {
+                            sp = e.ep2;
+                        } else if (!clp) {
+                            // the move aligns up with vp: |v - R u|^2 = az^2 + (|vp| - |up|)^2
+                            const float dd = sqrtf(dv2) - sqrtf(du2);
+                            sp = fmaf(az, az, dd * dd);
+                        } else {
+                            float sh, ch;
+                            sincosf(0.5f * dp, &sh, &ch);
+                            const float c2 = 1.f - 2.f * sh * sh, s2 = 2.f * sh * ch;
+                            const V3 rw = axpy(s2, cross(z, up), c2 * up);
+                            const V3 df = vp - rw;
+                            sp = fmaf(az, az, dot(df, df));
+                        }
+                        sP[j] = sqrtf(sp);
+                        dP[j] = dp;
+                        dmin = fminf(dmin, sP[j]);
+                        // eq. (ori_update): delta(k) sgn(a_hat . z) phi
+                        const float vzq = e.q.x * z.x + e.q.y * z.y + e.q.z * z.z;
+                        const float sg = vzq > 0.f ? 1.f : (vzq < 0.f ? -1.f : 0.f);
+                        const float dor = dk * sg * e.phi;
+                        const bool clo = (tj + dor > hi) || (tj + dor < lo);
+                        float ch = chu, sh = sg * shu;
+                        float doc = dor;
+                        if (clo) {
+                            doc = clampf(tj + dor, lo, hi) - tj;
+                            sincosf(0.5f * doc, &sh, &ch);
+                        }
+                        const Quat qn = qmul_conj_axis(e.q, z, ch, sh);
+                        const float v2 = qn.x * qn.x + qn.y * qn.y + qn.z * qn.z;
+                        sO[j] = 2.f * atan2f(sqrtf(v2), fabsf(qn.w));
+                        dO[j] = doc;
+                        omin = fminf(omin, sO[j]);
+                    }
+                }
+                // greedy picks: the lowest joint within tie_eps of the best score
+                int jp = -1, jo = -1;
+                float dpb = 0.f, dob = 0.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        if (jp < 0 && sP[j] <= dmin + kp.tie_eps) {
+                            jp = j;
+                            dpb = dP[j];
+                        }
+                        if (jo < 0 && sO[j] <= omin + kp.tie_eps) {
+                            jo = j;
+                            dob = dO[j];
+                        }
+                    }
+                }
+                // --- combine (Sec. IV-A): both moves, or the larger on one joint
+                int ja = jp, jb = jo;
+                float da = dpb, db = dob;
+                if (jp == jo) {
+                    if (fabsf(dpb) >= fabsf(dob)) {
+                        db = 0.f;
+                    } else {
+                        da = 0.f;
+                    }
+                    jb = ja;
+                    da = da + db;  // one of them is 0
+                    db = 0.f;
+                } else if (jo < jp) {
+                    ja = jo;
+                    jb = jp;
+                    da = dob;
+                    db = dpb;
+                }
+                // rigid update of the EE pose: distal move (jb) first, both axes
+                // taken at theta; ja <= jb.
+                V3 Pa = P[0], Za = Z[0], Pb = P[0], Zb = Z[0];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j == ja) {
+                        Pa = P[j];
+                        Za = Z[j];
+                    }
+                    if (j == jb) {
+                        Pb = P[j];
+                        Zb = Z[j];
+                    }
+                }
+                float sha, cha, shb, chb;
+                sincosf(0.5f * da, &sha, &cha);
+                sincosf(0.5f * db, &shb, &chb);
+                V3 ph = Pb + rot_half(Zb, chb, shb, ee.p - Pb);
+                ph = Pa + rot_half(Za, cha, sha, ph - Pa);
+                Quat qh = qmul_conj_axis(qmul_conj_axis(e.q, Zb, chb, shb), Za, cha, sha);
+                const V3 rph = tg.p - ph;
+                const float h2p = dot(rph, rph);
+                const float hs = sqrtf(qh.x * qh.x + qh.y * qh.y + qh.z * qh.z);
+                const float hphi = 2.f * atan2f(hs, fabsf(qh.w));
+                const bool acc = (e.ep2 - h2p > kp.gamma) || (e.phi * e.phi - hphi * hphi > kp.gamma);
+                if (acc) {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j) {
+                        if (j == ja) th[j] += da;
+                        if (j == jb) th[j] += db;
+                    }
+                } else {
+                    perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_CD, (uint32_t)k, kp.mu, kp.sigma);
+                    ++cnt.cd_perturb;
+                }
+            }
+        } else if (live) {
+            write_traj<NM>(traj, n, S, s, k, th, last_ep, last_phi);
+        }
+        delta *= kp.delta_decay;
+    }
+    Frame ee;
+    V3 Pd[1], Zd[1];
+    fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
+    out_err = residual(ee, tg);
+    if (live) write_traj<NM>(traj, n, S, s, kp.cd_sweeps, th, sqrtf(out_err.ep2), out_err.phi);
+}
+
+// ----------------------------------------------------------------------------
+// 6 x 6 Cholesky in registers (packed lower triangle, 21 entries)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+// In place: A (lower, packed) -> L with A = L L^T.  Returns false if a pivot
+// is not positive.
+__device__ __forceinline__ bool chol6(float* A) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        float s = A[tri(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s = fmaf(-A[tri(j, k)], A[tri(j, k)], s);
+        ok = ok && (s > 0.f);
+        const float l = sqrtf(fmaxf(s, 1e-30f));
+        const float il = 1.f / l;
+        A[tri(j, j)] = l;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            float t = A[tri(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t = fmaf(-A[tri(i, k)], A[tri(j, k)], t);
+            A[tri(i, j)] = t * il;
+        }
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void chol6_solve(const float* L, const float* b, float* x) {
+    float y[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        float t = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) t = fmaf(-L[tri(i, k)], y[k], t);
+        y[i] = t / L[tri(i, i)];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        float t = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k) t = fmaf(-L[tri(k, i)], x[k], t);
+        x[i] = t / L[tri(i, i)];
+    }
+}
+
+// Column j of J (eq. jacobian) with J stored as Jp[j] = z_j x (P_ee - P_j), Z[j].
+__device__ __forceinline__ void jcol(const V3* Jp, const V3* Z, int j, float* c) {
+    c[0] = Jp[j].x;
+    c[1] = Jp[j].y;
+    c[2] = Jp[j].z;
+    c[3] = Z[j].x;
+    c[4] = Z[j].y;
+    c[5] = Z[j].z;
+}
+
+template <int NM>
+__device__ __forceinline__ float trial_cost(const DevRobot* __restrict__ rb, int n, const Target& tg,
+                                            const float* tt) {
+    Frame ee;
+    V3 Pd[1], Zd[1];
+    fk_chain<NM, false>(rb, n, tt, Pd, Zd, ee);
+    return cost_of(residual(ee, tg));
+}
+
+// ----------------------------------------------------------------------------
+// PJ-IK (Alg. PJ-IK, Sec. IV-B) on one seed.
+// LM step: (J^T W^2 J + lam D) dtheta = J^T W^2 e is solved in its 6 x 6
+// push-through form dtheta = D^-1 J^T W (W J D^-1 J^T W + lam I)^-1 W e.
+// ----------------------------------------------------------------------------
+template <int NM>
+__device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
+                      uint32_t m, uint32_t tkey, float* th, bool live, Counters& cnt,
+                      float* __restrict__ traj, int64_t S, int64_t s, Err& out_err) {
+    bool frozen = !live;
+    float last_ep = 0.f, last_phi = 0.f;
+    V3 Jp[NM], Z[NM];
+    float dth[NM], tt[NM];
+    const float R = kp.trust_R;
+    for (int it = 0; it < kp.polish_iters; ++it) {
+        if (wave_all(frozen) && !traj) break;
+        bool done = true;  // lane needs no further fallback this iteration
+        float c0 = 0.f;
+        float e6[6], w6[6];
+        if (!frozen) {
+            Frame ee;
+            fk_chain<NM, true>(rb, n, th, Jp, Z, ee);
+            const Err e = residual(ee, tg);
+            last_ep = sqrtf(e.ep2);
+            last_phi = e.phi;
+            if (e.ep2 < kp.eps_pol2 && e.phi < kp.ups_pol) frozen = true;
+            if (live) write_traj<NM>(traj, n, S, s, it, th, last_ep, last_phi);
+            if (!frozen) {
+                ++cnt.pol_iters;
+                done = false;
+                c0 = cost_of(e);
+                const V3 om = omega_of(e);
+                e6[0] = e.rp.x;
+                e6[1] = e.rp.y;
+                e6[2] = e.rp.z;
+                e6[3] = om.x;
+                e6[4] = om.y;
+                e6[5] = om.z;
+                // Jacobian columns (eq. jacobian); row norms for W
+                float rn[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        Jp[j] = cross(Z[j], ee.p - Jp[j]);
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) rn[r] = fmaf(c[r], c[r], rn[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+                    w6[r] = kp.weight_mode == 0 ? 1.f / fmaxf(sqrtf(rn[r]), 1e-6f) : 1.f;
+                // A = W (sum_j J_j J_j^T / D_j) W + lam I,  D_j = |J_j|^2
+                float A[21];
+#pragma unroll
+                for (int i = 0; i < 21; ++i) A[i] = 0.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+                        float dj = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) dj = fmaf(c[r], c[r], dj);
+                        const float idj = 1.f / dj;
+#pragma unroll
+                        for (int a = 0; a < 6; ++a) {
+                            const float ca = c[a] * idj;
+#pragma unroll
+                            for (int b = 0; b <= a; ++b) A[tri(a, b)] = fmaf(ca, c[b], A[tri(a, b)]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+#pragma unroll
+                    for (int b = 0; b <= a; ++b)
+                        A[tri(a, b)] = A[tri(a, b)] * w6[a] * w6[b] + (a == b ? kp.lam : 0.f);
+                chol6(A);
+                float rhs[6], y[6];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) rhs[r] = w6[r] * e6[r];
+                chol6_solve(A, rhs, y);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) y[r] *= w6[r];
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+                        float dj = 0.f, g = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            dj = fmaf(c[r], c[r], dj);
+                            g = fmaf(c[r], y[r], g);
+                        }
+                        dth[j] = clampf(g / dj, -R, R);  // trust region, elementwise
+                    }
+                }
+            }
+        } else if (live) {
+            write_traj<NM>(traj, n, S, s, it, th, last_ep, last_phi);
+        }
+        // --- backtracking line search (eq. line-search), first decreasing alpha
+        float alpha = 1.f;
+        for (int i = 0; i <= kp.ls_A; ++i) {
+            if (wave_all(done)) break;
+            if (!done) {
+#pragma unroll
+                for (int j = 0; j < NM; ++j)
+                    if (j < n) tt[j] = clampf(fmaf(alpha, dth[j], th[j]), rb->lo[j], rb->hi[j]);
+                const float c1 = trial_cost<NM>(rb, n, tg, tt);
+                ++cnt.pol_trials;
+                if (c1 < c0) {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j < n) th[j] = tt[j];
+                    done = true;
+                }
+            }
+            alpha *= kp.inv_beta;
+        }
+        // --- dogleg fallback (eq. dogleg)
+        if (!wave_all(done)) {
+            if (!done) {
+                ++cnt.pol_dogleg;
+                // g = J^T e, Cauchy length |g|^2 / |J g|^2
+                float Jg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float gg = 0.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+                        float g = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) g = fmaf(c[r], e6[r], g);
+                        dth[j] = g;
+                        gg = fmaf(g, g, gg);
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) Jg[r] = fmaf(c[r], g, Jg[r]);
+                    }
+                }
+                float jgjg = 0.f;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) jgjg = fmaf(Jg[r], Jg[r], jgjg);
+                const float ac = jgjg > 0.f ? gg / jgjg : 0.f;
+                // Gauss-Newton: J^T (J J^T + lambda_gn I)^-1 e
+                float A[21];
+#pragma unroll
+                for (int i = 0; i < 21; ++i) A[i] = 0.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+#pragma unroll
+                        for (int a = 0; a < 6; ++a)
+#pragma unroll
+                            for (int b = 0; b <= a; ++b) A[tri(a, b)] = fmaf(c[a], c[b], A[tri(a, b)]);
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 6; ++a) A[tri(a, a)] += kp.lambda_gn;
+                chol6(A);
+                float y[6];
+                chol6_solve(A, e6, y);
+                float ngn2 = 0.f, ngd2 = 0.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+                        float g = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) g = fmaf(c[r], y[r], g);
+                        tt[j] = g;              // GN step
+                        dth[j] = ac * dth[j];   // GD step
+                        ngn2 = fmaf(g, g, ngn2);
+                        ngd2 = fmaf(dth[j], dth[j], ngd2);
+                    }
+                }
+                const float ngn = sqrtf(ngn2), ngd = sqrtf(ngd2);
+                // blend: tau = 0 if |GN| <= R; GD scaled to R if |GD| >= R; else the
+                // smaller root of |GN + tau (GD - GN)| = R
+                float tau = 0.f, scale_gd = 1.f;
+                bool use_gd = false;
+                if (ngn <= R) {
+                    tau = 0.f;
+                } else if (ngd >= R) {
+                    use_gd = true;
+                    scale_gd = R / ngd;
+                } else {
+                    float aa = 0.f, bb = 0.f;
+#pragma unroll
+                    for (int j = 0; j < NM; ++j) {
+                        if (j < n) {
+                            const float dj = dth[j] - tt[j];
+                            aa = fmaf(dj, dj, aa);
+                            bb = fmaf(tt[j], dj, bb);
+                        }
+                    }
+                    const float cc = ngn2 - R * R;
+                    const float den = -bb + sqrtf(fmaxf(bb * bb - aa * cc, 0.f));
+                    tau = den > 0.f ? clampf(cc / den, 0.f, 1.f) : 0.f;
+                }
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        const float st = use_gd ? scale_gd * dth[j] : fmaf(tau, dth[j] - tt[j], tt[j]);
+                        tt[j] = clampf(th[j] + st, rb->lo[j], rb->hi[j]);
+                    }
+                }
+                const float c1 = trial_cost<NM>(rb, n, tg, tt);
+                ++cnt.pol_trials;
+                if (c1 < c0) {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j < n) th[j] = tt[j];
+                    done = true;
+                }
+            }
+        }
+        // --- single-coordinate fallback (eq. single-coord)
+        if (!wave_all(done)) {
+            int is = 0;
+            float step = 0.f;
+            if (!done) {
+                ++cnt.pol_single;
+                float best = -1.f, gbest = 0.f, hbest = 1.f;
+#pragma unroll
+                for (int j = 0; j < NM; ++j) {
+                    if (j < n) {
+                        float c[6];
+                        jcol(Jp, Z, j, c);
+                        float g = 0.f, h = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 6; ++r) {
+                            const float w2 = w6[r] * w6[r];
+                            g = fmaf(c[r] * w2, e6[r], g);
+                            h = fmaf(c[r] * w2, c[r], h);
+                        }
+                        if (fabsf(g) > best) {
+                            best = fabsf(g);
+                            gbest = g;
+                            hbest = h;
+                            is = j;
+                        }
+                    }
+                }
+                step = hbest > 0.f ? clampf(gbest / hbest, -R, R) : 0.f;
+            }
+            float alpha2 = 1.f;
+            for (int i = 0; i <= kp.ls_A; ++i) {
+                if (wave_all(done)) break;
+                if (!done) {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j < n) tt[j] = (j == is) ? clampf(fmaf(alpha2, step, th[j]), rb->lo[j], rb->hi[j]) : th[j];
+                    const float c1 = trial_cost<NM>(rb, n, tg, tt);
+                    ++cnt.pol_trials;
+                    if (c1 < c0) {
+#pragma unroll
+                        for (int j = 0; j < NM; ++j)
+                            if (j < n) th[j] = tt[j];
+                        done = true;
+                    }
+                }
+                alpha2 *= kp.inv_beta;
+            }
+        }
+        // --- random perturbation when every step failed
+        if (!done) {
+            perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_POLISH, (uint32_t)it, kp.mu, kp.sigma);
+            ++cnt.pol_perturb;
+        }
+    }
+    Frame ee;
+    V3 Pd[1], Zd[1];
+    fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
+    out_err = residual(ee, tg);
+    if (live) write_traj<NM>(traj, n, S, s, kp.polish_iters, th, sqrtf(out_err.ep2), out_err.phi);
+}
+
+// ----------------------------------------------------------------------------
+// lane -> (seed slot, target, seed index within target)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int32_t last_le(const int64_t* __restrict__ a, int32_t count, int64_t v) {
+    // largest i in [0, count) with a[i] <= v (a non-decreasing, a[0] <= v)
+    int32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= v)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+struct Slot {
+    int64_t s;      // seed slot
+    int32_t t;      // target id
+    uint32_t m;     // seed index within the target
+    uint32_t tkey;  // Philox target key
+};
+
+__device__ __forceinline__ Slot map_lane(const SeedMap& mp, int64_t v) {
+    Slot r;
+    r.s = mp.base + v;
+    const int32_t b = mp.tb + last_le(mp.voffs + mp.tb, mp.te - mp.tb, r.s);
+    r.t = mp.tperm ? mp.tperm[b] : b;
+    r.m = (uint32_t)(r.s - mp.voffs[b]);
+    r.tkey = mp.tkeys ? mp.tkeys[r.t] : (uint32_t)r.t;
+    return r;
+}
+
+}  // namespace hjcd

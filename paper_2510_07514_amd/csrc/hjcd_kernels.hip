@@ -1,0 +1,420 @@
+// Kernels of libhjcd for gfx950 (CDNA4, wave64).  Citations refer to
+// arXiv 2510.07514.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hjcd_device.hpp"
+#include "hjcd_launch.hpp"
+
+namespace hjcd {
+
+// ----------------------------------------------------------------------------
+// FK + Jacobian of S configurations (eq. fk, eq. jacobian)
+// ----------------------------------------------------------------------------
+template <int NM>
+__global__ __launch_bounds__(256) void k_fk(const DevRobot* __restrict__ rb, int n, int64_t S,
+                                            const float* __restrict__ q, float* __restrict__ pose,
+                                            float* __restrict__ jac) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    float th[NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) th[j] = j < n ? q[(int64_t)j * S + s] : 0.f;
+    V3 P[NM], Z[NM];
+    Frame ee;
+    fk_chain<NM, true>(rb, n, th, P, Z, ee);
+    const Quat qe = quat_of(ee);
+    pose[s] = ee.p.x;
+    pose[S + s] = ee.p.y;
+    pose[2 * S + s] = ee.p.z;
+    pose[3 * S + s] = qe.w;
+    pose[4 * S + s] = qe.x;
+    pose[5 * S + s] = qe.y;
+    pose[6 * S + s] = qe.z;
+    if (jac) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            if (j < n) {
+                const V3 l = cross(Z[j], ee.p - P[j]);
+                const float c[6] = {l.x, l.y, l.z, Z[j].x, Z[j].y, Z[j].z};
+#pragma unroll
+                for (int r = 0; r < 6; ++r) jac[((int64_t)r * n + j) * S + s] = c[r];
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Collision filter (Sec. IV-C).  One wave per block; every link frame of a
+// lane goes to LDS ([link][12][64], lane fastest, conflict free).  For each
+// link the coarse enclosing sphere is tested first and the link's fine
+// spheres only when some lane's coarse test hits; a wave stops as soon as
+// all its lanes collide.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void lds_store_frame(float* lds, int l, int lane, const Frame& T) {
+    float* b = lds + (l * 12) * 64 + lane;
+    const float v[12] = {T.X.x, T.X.y, T.X.z, T.Y.x, T.Y.y, T.Y.z, T.Z.x, T.Z.y, T.Z.z, T.p.x, T.p.y, T.p.z};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) b[c * 64] = v[c];
+}
+
+__device__ __forceinline__ Frame lds_load_frame(const float* lds, int l, int lane) {
+    const float* b = lds + (l * 12) * 64 + lane;
+    Frame T;
+    T.X = mk(b[0], b[64], b[128]);
+    T.Y = mk(b[192], b[256], b[320]);
+    T.Z = mk(b[384], b[448], b[512]);
+    T.p = mk(b[576], b[640], b[704]);
+    return T;
+}
+
+__device__ __forceinline__ V3 xform(const Frame& T, float x, float y, float z) {
+    return axpy(z, T.Z, axpy(y, T.Y, axpy(x, T.X, T.p)));
+}
+
+__device__ __forceinline__ float box_d2(V3 c, const float* __restrict__ b) {
+    const float ex = fmaxf(0.f, fabsf(c.x - b[0]) - b[4]);
+    const float ey = fmaxf(0.f, fabsf(c.y - b[1]) - b[5]);
+    const float ez = fmaxf(0.f, fabsf(c.z - b[2]) - b[6]);
+    return fmaf(ex, ex, fmaf(ey, ey, ez * ez));
+}
+
+__global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = s < a.S;
+    const DevRobot* __restrict__ rb = a.rb;
+    const int n = a.n;
+    Frame T = identity_frame();
+    lds_store_frame(lds, 0, lane, T);
+    for (int i = 0; i < n; ++i) {
+        const float th = live ? a.q[(int64_t)i * a.q_stride + s] : 0.f;
+        chain_step(rb, i, th, T);
+        lds_store_frame(lds, i + 1, lane, T);
+    }
+    bool hit = !live;  // padding lanes count as done
+    uint32_t n_coarse = 0, n_fine = 0;
+    const float* __restrict__ os = a.osph;
+    const float* __restrict__ ob = a.obox;
+    // environment
+    for (int l = 0; l <= n && !wave_all(hit); ++l) {
+        const float Rc = rb->coarse[l][3];
+        if (Rc < 0.f) continue;
+        const Frame F = lds_load_frame(lds, l, lane);
+        const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
+        const int f0 = rb->link_first[l], fc = rb->link_count[l];
+        for (int o = 0; o < a.n_osph; ++o) {
+            const V3 co = mk(os[4 * o], os[4 * o + 1], os[4 * o + 2]);
+            const float ro = os[4 * o + 3];
+            const V3 d = cc - co;
+            const float rr = Rc + ro;
+            const bool ch = !hit && dot(d, d) < rr * rr;
+            n_coarse += hit ? 0u : 1u;
+            if (wave_any(ch)) {
+                for (int k = 0; k < fc; ++k) {
+                    const float* sp = rb->sph[f0 + k];
+                    if (ch && !hit) {
+                        const V3 c = xform(F, sp[0], sp[1], sp[2]);
+                        const V3 df = c - co;
+                        const float r2 = sp[3] + ro;
+                        ++n_fine;
+                        if (dot(df, df) < r2 * r2) hit = true;
+                    }
+                }
+                if (wave_all(hit)) break;
+            }
+        }
+        for (int o = 0; o < a.n_obox && !wave_all(hit); ++o) {
+            const float* b = ob + 8 * o;
+            const bool ch = !hit && box_d2(cc, b) < Rc * Rc;
+            n_coarse += hit ? 0u : 1u;
+            if (wave_any(ch)) {
+                for (int k = 0; k < fc; ++k) {
+                    const float* sp = rb->sph[f0 + k];
+                    if (ch && !hit) {
+                        const V3 c = xform(F, sp[0], sp[1], sp[2]);
+                        ++n_fine;
+                        if (box_d2(c, b) < sp[3] * sp[3]) hit = true;
+                    }
+                }
+            }
+        }
+    }
+    // self collision on the allowed link pairs
+    for (int pi = 0; pi < rb->n_pairs && !wave_all(hit); ++pi) {
+        const int la = rb->pair_a[pi], lb = rb->pair_b[pi];
+        const Frame Fa = lds_load_frame(lds, la, lane);
+        const Frame Fb = lds_load_frame(lds, lb, lane);
+        const V3 ca = xform(Fa, rb->coarse[la][0], rb->coarse[la][1], rb->coarse[la][2]);
+        const V3 cb = xform(Fb, rb->coarse[lb][0], rb->coarse[lb][1], rb->coarse[lb][2]);
+        const V3 d = ca - cb;
+        const float rr = rb->coarse[la][3] + rb->coarse[lb][3];
+        const bool ch = !hit && dot(d, d) < rr * rr;
+        n_coarse += hit ? 0u : 1u;
+        if (wave_any(ch)) {
+            const int fa = rb->link_first[la], na = rb->link_count[la];
+            const int fb = rb->link_first[lb], nb = rb->link_count[lb];
+            for (int i = 0; i < na; ++i) {
+                const float* sa = rb->sph[fa + i];
+                const V3 c1 = xform(Fa, sa[0], sa[1], sa[2]);
+                for (int k = 0; k < nb; ++k) {
+                    const float* sb = rb->sph[fb + k];
+                    if (ch && !hit) {
+                        const V3 c2 = xform(Fb, sb[0], sb[1], sb[2]);
+                        const V3 df = c1 - c2;
+                        const float r2 = sa[3] + sb[3];
+                        ++n_fine;
+                        if (dot(df, df) < r2 * r2) hit = true;
+                    }
+                }
+            }
+        }
+    }
+    if (live) a.flag[s] = hit ? 1 : 0;
+    if (a.counters) {
+        Counters c;
+        c.coll_coarse = live ? n_coarse : 0u;
+        c.coll_fine = live ? n_fine : 0u;
+        flush_counters(c, a.counters, true);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Per-target ordering by 64-bit keys, one wave per target.  Keys are unique
+// (they carry the seed index), so the r-th smallest key is the smallest key
+// above the (r-1)-th: k rounds of a lane-strided scan and a wave minimum.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, 64);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, 64);
+        const uint64_t w = ((uint64_t)hi << 32) | lo;
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t cost_key(float c, uint32_t m) {
+    const uint32_t b = __float_as_uint(c) & 0x7FFFFFFFu;  // costs are >= 0
+    return ((uint64_t)b << 32) | m;
+}
+
+// Final selection (Alg. HJCD-IK, last line): order (flag != 0, cost, index).
+__global__ __launch_bounds__(64) void k_select(SelectArgs a) {
+    const int b = blockIdx.x;
+    const int t = a.tperm ? a.tperm[b] : b;
+    const int lane = threadIdx.x;
+    const int64_t b0 = a.offsets[b];
+    const int64_t M = a.offsets[b + 1] - b0;
+    uint32_t nf = 0;
+    for (int64_t m = lane; m < M; m += 64) nf += a.flag[b0 + m] == 0 ? 1u : 0u;
+    nf = wave_sum(nf);
+    uint64_t prev = 0;
+    bool ok = false;
+    for (int r = 0; r < a.k; ++r) {
+        uint64_t best = ~0ull;
+        for (int64_t m = lane; m < M; m += 64) {
+            const uint64_t key = ((uint64_t)(a.flag[b0 + m] != 0) << 63) |
+                                 cost_key(a.cost[b0 + m], (uint32_t)m);
+            if ((r == 0 || key > prev) && key < best) best = key;
+        }
+        best = wave_min_u64(best);
+        const int64_t o = (int64_t)t * a.k + r;
+        if (best == ~0ull) {
+            if (lane < a.n_stride) a.q_out[o * a.n_stride + lane] = 0.f;
+            if (lane == 0) {
+                a.ep_out[o] = __builtin_inff();
+                a.eo_out[o] = __builtin_inff();
+                a.fl_out[o] = 255;
+            }
+            continue;
+        }
+        prev = best;
+        const int64_t s = b0 + (int64_t)(uint32_t)best;
+        if (lane < a.n_stride) a.q_out[o * a.n_stride + lane] = lane < a.n ? a.q[(int64_t)lane * a.S + s] : 0.f;
+        const float ep = a.err_p[s], eo = a.err_o[s];
+        const uint8_t fl = a.flag[s];
+        if (lane == 0) {
+            a.ep_out[o] = ep;
+            a.eo_out[o] = eo;
+            a.fl_out[o] = fl;
+        }
+        ok = ok || (fl == 0 && ep <= a.succ_pos && eo <= a.succ_ori);
+    }
+    if (lane == 0) {
+        a.n_free[t] = (int32_t)nf;
+        a.solved[t] = ok ? 1 : 0;
+    }
+}
+
+// Mid top-K ranking (Alg. HJCD-IK): K smallest (cost, index) per target.
+__global__ __launch_bounds__(64) void k_rank(int32_t T, const int64_t* __restrict__ offsets,
+                                             const float* __restrict__ cost, int32_t K,
+                                             int32_t* __restrict__ rank) {
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t b0 = offsets[t];
+    const int64_t M = offsets[t + 1] - b0;
+    uint64_t prev = 0;
+    for (int r = 0; r < K; ++r) {
+        if (r >= M) {
+            if (lane == 0) rank[(int64_t)t * K + r] = M > 0 ? rank[(int64_t)t * K + (r % M)] : -1;
+            continue;
+        }
+        uint64_t best = ~0ull;
+        for (int64_t m = lane; m < M; m += 64) {
+            const uint64_t key = cost_key(cost[b0 + m], (uint32_t)m);
+            if ((r == 0 || key > prev) && key < best) best = key;
+        }
+        best = wave_min_u64(best);
+        prev = best;
+        if (lane == 0) rank[(int64_t)t * K + r] = (int32_t)(uint32_t)best;
+    }
+}
+
+// Noisy copies: slot b*Bp + i*K + kk <- clip(q[rank kk] + mu + sigma z).
+template <int NM>
+__global__ __launch_bounds__(256) void k_replicate(const DevRobot* __restrict__ rb, int n, int32_t tb,
+                                                   int32_t te, const int64_t* __restrict__ offsets,
+                                                   const int32_t* __restrict__ tperm, int64_t S_in,
+                                                   const float* __restrict__ q_in,
+                                                   const int32_t* __restrict__ rank, int32_t K, int32_t Bp,
+                                                   const uint32_t* __restrict__ tkeys, uint64_t seed,
+                                                   float mu, float sigma, float* __restrict__ q_out,
+                                                   int64_t Sout) {
+    const int64_t v = (int64_t)tb * Bp + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= (int64_t)te * Bp) return;
+    const int32_t b = (int32_t)(v / Bp);
+    const int32_t j = (int32_t)(v % Bp);
+    const int32_t kk = j % K;
+    const int64_t src = offsets[b] + rank[(int64_t)b * K + kk];
+    const int32_t t = tperm ? tperm[b] : b;
+    float th[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) th[i] = i < n ? q_in[(int64_t)i * S_in + src] : 0.f;
+    perturb<NM>(rb, n, th, seed, (uint32_t)j, tkeys ? tkeys[t] : (uint32_t)t, STAGE_RESAMPLE, 0, mu, sigma);
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        if (i < n) q_out[(int64_t)i * Sout + v] = th[i];
+}
+
+// Caller layout -> robot-grouped layout.
+__global__ __launch_bounds__(256) void k_gather(int n, int32_t T, const int64_t* __restrict__ offsets,
+                                                const int64_t* __restrict__ voffs,
+                                                const int32_t* __restrict__ tperm, int64_t S,
+                                                int64_t in_stride, const float* __restrict__ q_in,
+                                                float* __restrict__ q_out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= S) return;
+    const int32_t b = last_le(voffs, T, v);
+    const int32_t t = tperm ? tperm[b] : b;
+    const int64_t src = offsets[t] + (v - voffs[b]);
+    for (int i = 0; i < n; ++i) q_out[(int64_t)i * S + v] = q_in[(int64_t)i * in_stride + src];
+}
+
+__global__ void k_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                         int64_t count, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const U4 r = philox(U4{c0 + (uint32_t)i, c1, c2, c3}, k0, k1);
+    out[4 * i] = r.a;
+    out[4 * i + 1] = r.b;
+    out[4 * i + 2] = r.c;
+    out[4 * i + 3] = r.d;
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+static inline unsigned blocks_for(int64_t count, int per) { return (unsigned)((count + per - 1) / per); }
+
+#define HJCD_DISPATCH_NM(n, CALL) \
+    do {                          \
+        if ((n) <= 8) {           \
+            CALL(8);              \
+        } else if ((n) <= 16) {   \
+            CALL(16);             \
+        } else if ((n) <= 24) {   \
+            CALL(24);             \
+        } else {                  \
+            CALL(32);             \
+        }                         \
+    } while (0)
+
+template <int NM>
+hipError_t launch_solve_nm(const SolveArgs& a, hipStream_t st);
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t st) {
+    if (a.map.Sv <= 0) return hipSuccess;
+#define L_SOLVE(NMV) return launch_solve_nm<NMV>(a, st)
+    HJCD_DISPATCH_NM(a.n, L_SOLVE);
+#undef L_SOLVE
+}
+
+hipError_t launch_fk(const DevRobot* rb, int n, int64_t S, const float* q, float* pose, float* jac,
+                     hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    const unsigned nb = blocks_for(S, 256);
+#define L_FK(NMV) hipLaunchKernelGGL(k_fk<NMV>, dim3(nb), dim3(256), 0, st, rb, n, S, q, pose, jac)
+    HJCD_DISPATCH_NM(n, L_FK);
+#undef L_FK
+    return hipGetLastError();
+}
+
+hipError_t launch_collide(const CollideArgs& a, hipStream_t st) {
+    if (a.S <= 0) return hipSuccess;
+    const size_t lds = (size_t)(a.n + 1) * 12 * 64 * sizeof(float);
+    hipLaunchKernelGGL(k_collide, dim3(blocks_for(a.S, 64)), dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs& a, hipStream_t st) {
+    if (a.T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3(a.T), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(int32_t T, const int64_t* offsets, const float* cost, int32_t K, int32_t* rank,
+                       hipStream_t st) {
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rank, dim3(T), dim3(64), 0, st, T, offsets, cost, K, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_replicate(const DevRobot* rb, int n, int32_t tb, int32_t te, int32_t T,
+                            const int64_t* offsets, const int32_t* tperm, int64_t S_in,
+                            const float* q_in, const int32_t* rank, int32_t K, int32_t Bp,
+                            const uint32_t* tkeys, uint64_t seed, float mu, float sigma, float* q_out,
+                            hipStream_t st) {
+    const int64_t cnt = (int64_t)(te - tb) * Bp;
+    if (cnt <= 0) return hipSuccess;
+    const int64_t Sout = (int64_t)T * Bp;
+    const unsigned nb = blocks_for(cnt, 256);
+#define L_REP(NMV)                                                                                  \
+    hipLaunchKernelGGL(k_replicate<NMV>, dim3(nb), dim3(256), 0, st, rb, n, tb, te, offsets, tperm, \
+                       S_in, q_in, rank, K, Bp, tkeys, seed, mu, sigma, q_out, Sout)
+    HJCD_DISPATCH_NM(n, L_REP);
+#undef L_REP
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int n, int32_t T, const int64_t* offsets, const int64_t* voffs,
+                         const int32_t* tperm, int64_t S, int64_t in_stride, const float* q_in,
+                         float* q_out, hipStream_t st) {
+    if (S <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(S, 256)), dim3(256), 0, st, n, T, offsets, voffs, tperm, S,
+                       in_stride, q_in, q_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                         int64_t count, uint32_t* out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(count, 256)), dim3(256), 0, st, c0, c1, c2, c3, k0, k1,
+                       count, out);
+    return hipGetLastError();
+}
+
+}  // namespace hjcd

@@ -1,0 +1,126 @@
+// Internal launch interface between the C ABI (hjcd_api.cpp) and the kernels
+// (hjcd_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hjcd_tables.hpp"
+
+namespace hjcd {
+
+// Seeds live in a robot-grouped slot layout: targets are permuted so that
+// the targets of one robot are consecutive (tperm: permuted position ->
+// target id, nullptr = identity) and voffs [T+1] is the CSR of seed slots
+// over the permuted targets.  One launch covers the permuted targets
+// [tb, te) of one robot, i.e. the slots [base, base + Sv).
+struct SeedMap {
+    const int64_t* voffs;    // [T+1] device
+    const int32_t* tperm;    // [T] device or nullptr
+    int32_t T;
+    int32_t tb, te;
+    int64_t base, Sv;
+    const uint32_t* tkeys;   // [T] by target id, device or nullptr
+};
+
+struct KernelParams {
+    int32_t cd_sweeps, polish_iters, ls_A, weight_mode;
+    float eps_cd2, nu_cd, gamma, delta0, delta_decay, delta_min, proj_eps2, tie_eps;
+    float lam, lambda_gn, trust_R, inv_beta;
+    float eps_pol2, ups_pol, sigma, mu;
+    uint64_t seed;
+};
+
+enum InitMode { INIT_LOAD = 0, INIT_UNIFORM = 1 };
+
+// Per-seed CD and/or PJ-IK over the slots of `map`.  q_in [n][q_in_stride]
+// (INIT_LOAD) or unused; q_out [n][S] (may alias q_in); err_p / err_o / cost
+// [S] nullable; traj [rows][n+2][S] nullable.
+struct SolveArgs {
+    const DevRobot* rb;
+    int32_t n;
+    int32_t n_rows;          // q_out rows n..n_rows-1 are written as 0 (mixed-dof batches)
+    SeedMap map;
+    int64_t S;               // seed slots (row stride of q arrays)
+    const float* targets;    // [7][T]
+    const float* q_in;
+    int64_t q_in_stride;     // row stride of q_in (usually S)
+    float* q_out;
+    float* err_p;
+    float* err_o;
+    float* cost;
+    float* traj;
+    int32_t init_mode;
+    int32_t do_cd, do_polish;
+    KernelParams kp;
+    unsigned long long* counters;  // [9] or nullptr
+};
+
+hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
+
+hipError_t launch_fk(const DevRobot* rb, int n, int64_t S, const float* q, float* pose, float* jac,
+                     hipStream_t st);
+
+struct CollideArgs {
+    const DevRobot* rb;
+    int32_t n;
+    int64_t S;
+    const float* q;          // [n][q_stride]
+    int64_t q_stride;
+    const float* osph;       // [n_osph][4]
+    int32_t n_osph;
+    const float* obox;       // [n_obox][8]: cx cy cz 0 hx hy hz 0
+    int32_t n_obox;
+    uint8_t* flag;
+    unsigned long long* counters;
+};
+
+hipError_t launch_collide(const CollideArgs& a, hipStream_t st);
+
+struct SelectArgs {
+    int32_t T;
+    const int64_t* offsets;  // [T+1] device, CSR over permuted targets
+    const int32_t* tperm;    // [T] permuted position -> target id, nullptr = identity
+    int32_t n, n_stride;
+    int64_t S;
+    const float* q;          // [n][S]
+    const float* cost;
+    const float* err_p;
+    const float* err_o;
+    const uint8_t* flag;
+    int32_t k;
+    float succ_pos, succ_ori;
+    float* q_out;
+    float* ep_out;
+    float* eo_out;
+    uint8_t* fl_out;
+    int32_t* n_free;
+    uint8_t* solved;
+};
+
+hipError_t launch_select(const SelectArgs& a, hipStream_t st);
+
+// Mid top-K ranking over permuted targets: rank [T][K] = seed indices
+// (within target) of the K smallest (cost, index); rank r >= M repeats rank
+// r % M.
+hipError_t launch_rank(int32_t T, const int64_t* offsets, const float* cost, int32_t K, int32_t* rank,
+                       hipStream_t st);
+
+// Noisy replication for the permuted targets [tb, te): slot b*Bp + i*K + kk
+// of q_out [n][T*Bp] <- q_in [n][S_in] at offsets[b] + rank[b][kk].
+hipError_t launch_replicate(const DevRobot* rb, int n, int32_t tb, int32_t te, int32_t T,
+                            const int64_t* offsets, const int32_t* tperm, int64_t S_in,
+                            const float* q_in, const int32_t* rank, int32_t K, int32_t Bp,
+                            const uint32_t* tkeys, uint64_t seed, float mu, float sigma, float* q_out,
+                            hipStream_t st);
+
+// Gather caller-layout seeds [n][S] (CSR `offsets` by target id) into the
+// robot-grouped layout q_out [n][S] (CSR `voffs` over permuted targets).
+hipError_t launch_gather(int n, int32_t T, const int64_t* offsets, const int64_t* voffs,
+                         const int32_t* tperm, int64_t S, int64_t in_stride, const float* q_in,
+                         float* q_out, hipStream_t st);
+
+hipError_t launch_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                         int64_t count, uint32_t* out, hipStream_t st);
+
+}  // namespace hjcd

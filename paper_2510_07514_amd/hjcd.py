@@ -1,0 +1,348 @@
+"""Python binding of libhjcd (the C ABI in include/hjcd.h), same names.
+
+Argument marshalling only: torch tensors supply device memory and streams,
+every step of the solve runs in the library's HIP kernels.  Importing this
+module fails loudly when libhjcd.so has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhjcd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_07514_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+HJCD_OK = 0
+HJCD_E_INVALID = -1
+HJCD_E_NOMEM = -2
+HJCD_E_DEVICE = -3
+HJCD_E_UNSUPPORTED = -4
+HJCD_E_BUSY = -5
+HJCD_E_INTERNAL = -6
+HJCD_MAX_DOF = 32
+HJCD_MAX_TOPK = 64
+
+SYMBOLS = ("hjcd_ctx_create", "hjcd_ctx_destroy", "hjcd_last_error", "hjcd_params_default",
+           "hjcd_version", "hjcd_load_robot", "hjcd_robot_destroy", "hjcd_robot_dof",
+           "hjcd_load_scene", "hjcd_scene_destroy", "hjcd_fk", "hjcd_init_seeds", "hjcd_cd",
+           "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve",
+           "hjcd_get_stats", "hjcd_philox")
+
+
+class HJCDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hjcd status {status}: {msg}")
+        self.status = status
+
+
+class hjcd_robot_desc(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("convention", C.c_int32),
+                ("a", C.POINTER(C.c_double)), ("d", C.POINTER(C.c_double)),
+                ("alpha", C.POINTER(C.c_double)), ("offset", C.POINTER(C.c_double)),
+                ("q_min", C.POINTER(C.c_double)), ("q_max", C.POINTER(C.c_double)),
+                ("tool", C.POINTER(C.c_double)), ("n_spheres", C.c_int32),
+                ("sphere_link", C.POINTER(C.c_int32)), ("sphere_xyzr", C.POINTER(C.c_double)),
+                ("min_link_gap", C.c_int32)]
+
+
+class hjcd_params(C.Structure):
+    _fields_ = [("cd_sweeps", C.c_int32), ("polish_iters", C.c_int32),
+                ("eps_cd", C.c_float), ("nu_cd", C.c_float), ("gamma", C.c_float),
+                ("delta0", C.c_float), ("delta_decay", C.c_float), ("delta_min", C.c_float),
+                ("proj_eps", C.c_float), ("tie_eps", C.c_float), ("lambda_", C.c_float), ("lambda_gn", C.c_float),
+                ("trust_R", C.c_float), ("ls_beta", C.c_float), ("ls_A", C.c_int32),
+                ("weight_mode", C.c_int32), ("eps_pol", C.c_float), ("ups_pol", C.c_float),
+                ("sigma", C.c_float), ("mu", C.c_float), ("resample_K", C.c_int32),
+                ("resample_B", C.c_int32), ("top_k", C.c_int32), ("succ_pos", C.c_float),
+                ("succ_ori", C.c_float), ("rng_seed", C.c_uint64), ("collect_stats", C.c_int32)]
+
+
+class hjcd_stats(C.Structure):
+    _fields_ = [("ms_init", C.c_float), ("ms_cd", C.c_float), ("ms_resample", C.c_float),
+                ("ms_polish", C.c_float), ("ms_collide", C.c_float), ("ms_select", C.c_float),
+                ("ms_solve_kernel", C.c_float), ("ms_total", C.c_float),
+                ("seeds", C.c_uint64), ("cd_iters", C.c_uint64), ("cd_perturb", C.c_uint64),
+                ("pol_iters", C.c_uint64), ("pol_trials", C.c_uint64), ("pol_dogleg", C.c_uint64),
+                ("pol_single", C.c_uint64), ("pol_perturb", C.c_uint64),
+                ("coll_coarse", C.c_uint64), ("coll_fine", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = C.c_void_p
+_i32, _i64, _u64 = C.c_int32, C.c_int64, C.c_uint64
+_lib.hjcd_ctx_create.argtypes = [C.c_int, C.POINTER(_vp)]
+_lib.hjcd_ctx_destroy.argtypes = [_vp]
+_lib.hjcd_last_error.restype = C.c_char_p
+_lib.hjcd_version.restype = C.c_char_p
+_lib.hjcd_params_default.argtypes = [C.POINTER(hjcd_params)]
+_lib.hjcd_load_robot.argtypes = [_vp, C.POINTER(hjcd_robot_desc), C.POINTER(_vp)]
+_lib.hjcd_robot_destroy.argtypes = [_vp]
+_lib.hjcd_robot_dof.argtypes = [_vp]
+_lib.hjcd_load_scene.argtypes = [_vp, _i32, _vp, _i32, _vp, C.POINTER(_vp)]
+_lib.hjcd_scene_destroy.argtypes = [_vp]
+_lib.hjcd_fk.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp]
+_lib.hjcd_init_seeds.argtypes = [_vp, _vp, _i32, _vp, _vp, _u64, _vp, _vp]
+_stage = [_vp, _vp, _i32, _vp, _vp, _vp, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_cd.argtypes = _stage
+_lib.hjcd_polish.argtypes = _stage
+_lib.hjcd_collide.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
+_lib.hjcd_resample.argtypes = [_vp, _vp, _i32, _vp, _vp, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp]
+_lib.hjcd_select.argtypes = [_vp, _i32, _vp, _i32, _i32, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp,
+                             _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_solve.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                            C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_get_stats.argtypes = [_vp, C.POINTER(hjcd_stats)]
+_lib.hjcd_philox.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+for _name in SYMBOLS:
+    if _name not in ("hjcd_ctx_destroy", "hjcd_robot_destroy", "hjcd_scene_destroy",
+                     "hjcd_last_error", "hjcd_version", "hjcd_params_default"):
+        getattr(_lib, _name).restype = C.c_int32
+
+
+def _check(status):
+    if status != HJCD_OK:
+        raise HJCDError(status, _lib.hjcd_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libhjcd must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+# ---------------------------------------------------------------------------
+# handles
+# ---------------------------------------------------------------------------
+
+class Context:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            _lib.hjcd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Robot:
+    def __init__(self, ctx, handle, dof):
+        self.ctx, self.handle, self.dof = ctx, handle, dof
+
+    def close(self):
+        if self.handle:
+            _lib.hjcd_robot_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    def __init__(self, ctx, handle):
+        self.ctx, self.handle = ctx, handle
+
+    def close(self):
+        if self.handle:
+            _lib.hjcd_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hjcd_version():
+    return _lib.hjcd_version().decode()
+
+
+def hjcd_last_error():
+    return _lib.hjcd_last_error().decode()
+
+
+def hjcd_params_default(**over) -> hjcd_params:
+    p = hjcd_params()
+    _lib.hjcd_params_default(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def params_from_dict(d: dict, collect_stats: bool = False) -> hjcd_params:
+    """hjcd_params from the workload module's parameter dict."""
+    p = hjcd_params_default()
+    for k, v in d.items():
+        name = "lambda_" if k == "lam" else k
+        if any(f == name for f, _ in hjcd_params._fields_):
+            setattr(p, name, v)
+    p.collect_stats = 1 if collect_stats else 0
+    return p
+
+
+def hjcd_ctx_create(device: int = 0) -> Context:
+    h = _vp()
+    _check(_lib.hjcd_ctx_create(device, C.byref(h)))
+    return Context(h.value)
+
+
+def hjcd_ctx_destroy(ctx: Context):
+    ctx.close()
+
+
+def hjcd_load_robot(ctx: Context, robot) -> Robot:
+    """robot: any object with dof, convention, a, d, alpha, offset, q_min,
+    q_max, tool (4x4), sphere_link, sphere_xyzr, min_link_gap."""
+    bufs = [_host(getattr(robot, k), np.float64)[0] for k in ("a", "d", "alpha", "offset", "q_min", "q_max")]
+    tool = _host(np.asarray(robot.tool).reshape(16), np.float64)[0]
+    sl = _host(robot.sphere_link, np.int32)[0]
+    sx = _host(np.asarray(robot.sphere_xyzr).reshape(-1), np.float64)[0]
+    dp = C.POINTER(C.c_double)
+    desc = hjcd_robot_desc(int(robot.dof), int(robot.convention),
+                           *[b.ctypes.data_as(dp) for b in bufs], tool.ctypes.data_as(dp),
+                           int(sl.shape[0]), sl.ctypes.data_as(C.POINTER(C.c_int32)),
+                           sx.ctypes.data_as(dp), int(robot.min_link_gap))
+    h = _vp()
+    _check(_lib.hjcd_load_robot(ctx.handle, C.byref(desc), C.byref(h)))
+    return Robot(ctx, h.value, int(robot.dof))
+
+
+def hjcd_robot_destroy(robot: Robot):
+    robot.close()
+
+
+def hjcd_robot_dof(robot: Robot) -> int:
+    return _lib.hjcd_robot_dof(robot.handle)
+
+
+def hjcd_load_scene(ctx: Context, spheres, boxes) -> Scene:
+    s, sp = _host(np.asarray(spheres).reshape(-1), np.float32)
+    b, bp = _host(np.asarray(boxes).reshape(-1), np.float32)
+    h = _vp()
+    _check(_lib.hjcd_load_scene(ctx.handle, int(s.shape[0] // 4), sp if s.size else None,
+                                int(b.shape[0] // 6), bp if b.size else None, C.byref(h)))
+    return Scene(ctx, h.value)
+
+
+def hjcd_scene_destroy(scene: Scene):
+    scene.close()
+
+
+# ---------------------------------------------------------------------------
+# stages
+# ---------------------------------------------------------------------------
+
+def hjcd_fk(ctx, robot, q, pose, jac=None, stream=None):
+    """q float32 [n][S] -> pose float32 [7][S], jac [6][n][S] (optional)."""
+    S = q.shape[1] if q.dim() == 2 else 0
+    _check(_lib.hjcd_fk(ctx.handle, robot.handle, S, _ptr(q), _ptr(pose), _ptr(jac), _stream(stream)))
+
+
+def hjcd_init_seeds(ctx, robot, seed_offsets, q, rng_seed, target_keys=None, stream=None):
+    offs, op = _host(seed_offsets, np.int64)
+    _check(_lib.hjcd_init_seeds(ctx.handle, robot.handle, int(offs.shape[0] - 1), op, _ptr(target_keys),
+                                int(rng_seed), _ptr(q), _stream(stream)))
+
+
+def _stage(fn, ctx, robot, targets, seed_offsets, params, q, err_p, err_o, cost, traj, target_keys,
+           stream):
+    offs, op = _host(seed_offsets, np.int64)
+    _check(fn(ctx.handle, robot.handle, int(offs.shape[0] - 1), _ptr(targets), op, _ptr(target_keys),
+              C.byref(params), _ptr(q), _ptr(err_p), _ptr(err_o), _ptr(cost), _ptr(traj),
+              _stream(stream)))
+
+
+def hjcd_cd(ctx, robot, targets, seed_offsets, params, q, err_p=None, err_o=None, cost=None, traj=None,
+            target_keys=None, stream=None):
+    _stage(_lib.hjcd_cd, ctx, robot, targets, seed_offsets, params, q, err_p, err_o, cost, traj,
+           target_keys, stream)
+
+
+def hjcd_polish(ctx, robot, targets, seed_offsets, params, q, err_p=None, err_o=None, cost=None,
+                traj=None, target_keys=None, stream=None):
+    _stage(_lib.hjcd_polish, ctx, robot, targets, seed_offsets, params, q, err_p, err_o, cost, traj,
+           target_keys, stream)
+
+
+def hjcd_collide(ctx, robot, scene, q, flag, stream=None):
+    S = q.shape[1] if q.dim() == 2 else 0
+    _check(_lib.hjcd_collide(ctx.handle, robot.handle, scene.handle if scene else None, S, _ptr(q),
+                             _ptr(flag), _stream(stream)))
+
+
+def hjcd_resample(ctx, robot, seed_offsets, params, q_in, cost_in, q_out, target_keys=None,
+                  stream=None):
+    offs, op = _host(seed_offsets, np.int64)
+    _check(_lib.hjcd_resample(ctx.handle, robot.handle, int(offs.shape[0] - 1), op, _ptr(target_keys),
+                              C.byref(params), _ptr(q_in), _ptr(cost_in), _ptr(q_out), _stream(stream)))
+
+
+def hjcd_select(ctx, seed_offsets, n, n_stride, params, q, cost, err_p, err_o, flag, q_out, err_p_out,
+                err_o_out, flag_out, n_free, solved, stream=None):
+    offs, op = _host(seed_offsets, np.int64)
+    _check(_lib.hjcd_select(ctx.handle, int(offs.shape[0] - 1), op, int(n), int(n_stride),
+                            C.byref(params), _ptr(q), _ptr(cost), _ptr(err_p), _ptr(err_o), _ptr(flag),
+                            _ptr(q_out), _ptr(err_p_out), _ptr(err_o_out), _ptr(flag_out),
+                            _ptr(n_free), _ptr(solved), _stream(stream)))
+
+
+def hjcd_solve(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, err_o, flag, n_free,
+               solved, robot_of_target=None, seeds=None, target_keys=None, stream=None):
+    """The whole batched solve; see hjcd_solve in include/hjcd.h."""
+    if isinstance(robots, Robot):
+        robots = [robots]
+    arr = (_vp * len(robots))(*[r.handle for r in robots])
+    offs, op = _host(seed_offsets, np.int64)
+    rot = None
+    if robot_of_target is not None:
+        rot, rotp = _host(robot_of_target, np.int32)
+    _check(_lib.hjcd_solve(ctx.handle, len(robots), C.cast(arr, _vp), scene.handle if scene else None,
+                           int(offs.shape[0] - 1), rotp if rot is not None else None, _ptr(targets), op,
+                           _ptr(target_keys), _ptr(seeds), C.byref(params), _ptr(q_out), _ptr(err_p),
+                           _ptr(err_o), _ptr(flag), _ptr(n_free), _ptr(solved), _stream(stream)))
+
+
+def hjcd_get_stats(ctx) -> dict:
+    st = hjcd_stats()
+    _check(_lib.hjcd_get_stats(ctx.handle, C.byref(st)))
+    return st.as_dict()
+
+
+def hjcd_philox(ctx, ctr, key, count, out, stream=None):
+    c, cp = _host(ctr, np.uint32)
+    k, kp = _host(key, np.uint32)
+    _check(_lib.hjcd_philox(ctx.handle, cp, kp, int(count), _ptr(out), _stream(stream)))

@@ -1,0 +1,452 @@
+"""GPU parity: every stage of libhjcd (through the C ABI) against the FP64
+oracle on the same seeded inputs.  Run on an MI355X: pytest -m gpu."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_common import TAU_DEC, TOL_TRAJ, compare_trajectories, cuda, quat_close, say, soa, targets_soa
+from paper_2510_07514_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_07514_amd import hjcd
+    return hjcd
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.hjcd_ctx_create(0)
+    yield c
+    c.close()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# random numbers
+# ---------------------------------------------------------------------------
+
+def test_philox_bitwise(H, ctx):
+    import torch
+    say("case: philox known answers + 65536 counters")
+    for ctr, key, want in [([0, 0, 0, 0], [0, 0], [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]),
+                           ([0xffffffff] * 4, [0xffffffff] * 2, [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]),
+                           ([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344], [0xa4093822, 0x299f31d0],
+                            [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1])]:
+        out = torch.zeros(4, dtype=torch.int32, device="cuda")
+        H.hjcd_philox(ctx, ctr, key, 1, out)
+        _sync()
+        assert np.array_equal(out.cpu().numpy().view(np.uint32), np.array(want, np.uint32))
+    rng = np.random.default_rng(0)
+    for _ in range(4):
+        ctr = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64).astype(np.uint32)
+        key = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64).astype(np.uint32)
+        cnt = 16384
+        out = torch.zeros(4 * cnt, dtype=torch.int32, device="cuda")
+        H.hjcd_philox(ctx, ctr, key, cnt, out)
+        _sync()
+        g = out.cpu().numpy().view(np.uint32).reshape(cnt, 4)
+        for i in range(0, cnt, 997):
+            c = ctr.copy()
+            c[0] = np.uint32((int(ctr[0]) + i) & 0xFFFFFFFF)
+            assert np.array_equal(g[i], O.philox(c, key)), i
+
+
+# ---------------------------------------------------------------------------
+# forward kinematics and Jacobian
+# ---------------------------------------------------------------------------
+
+def _robots():
+    rng = np.random.default_rng(5)
+    return {"panda": W.config_batched(T=1, M=1).robots[0], "ur": W.ur_like(),
+            "random12": W.random_chain(rng, 12), "random20": W.config_large(T=1, M=1).robots[0],
+            "planar3": W.planar_chain([0.5, 0.4, 0.3])}
+
+
+@pytest.mark.parametrize("name", ["panda", "ur", "random12", "random20", "planar3"])
+def test_fk_and_jacobian(H, ctx, name):
+    import torch
+    say(f"case: fk {name}")
+    rob = _robots()[name]
+    rb = H.hjcd_load_robot(ctx, rob)
+    rng = np.random.default_rng(1)
+    S = 1000 + 37  # several waves and a ragged tail
+    q = W.uniform_configs(rng, rob, S)
+    n = rob.dof
+    pose = torch.zeros(7, S, device="cuda")
+    jac = torch.zeros(6, n, S, device="cuda")
+    H.hjcd_fk(ctx, rb, soa(q, n), pose, jac)
+    _sync()
+    pose = pose.cpu().numpy()
+    jac = jac.cpu().numpy()
+    rh = O.RobotHandle(rob)
+    for s in range(0, S, 13):
+        f = O.fk(rh, q[s].astype(np.float64))
+        assert np.max(np.abs(pose[:3, s] - f["p_ee"])) < 1e-5
+        assert quat_close(pose[3:, s], f["quat"]) < 1e-5
+        assert pose[3, s] >= 0
+        assert np.max(np.abs(jac[:, :, s] - f["J"])) < 1e-5
+
+
+def test_uniform_seeds(H, ctx):
+    import torch
+    say("case: uniform seeds")
+    rob = W.panda_like()
+    rb = H.hjcd_load_robot(ctx, rob)
+    offs = np.array([0, 100, 100, 357], np.int64)
+    q = torch.zeros(7, 357, device="cuda")
+    H.hjcd_init_seeds(ctx, rb, offs, q, rng_seed=12345)
+    _sync()
+    q = q.cpu().numpy()
+    for t in range(3):
+        for m in range(int(offs[t + 1] - offs[t])):
+            ref = O.uniform_seed(rob, 12345, m, t)
+            assert np.max(np.abs(q[:, offs[t] + m] - ref)) < 2e-6
+
+
+# ---------------------------------------------------------------------------
+# collision
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["tiny", "batched", "large"])
+def test_collision_flags(H, ctx, which):
+    import torch
+    say(f"case: collide {which}")
+    b = {"tiny": W.config_tiny(), "batched": W.config_batched(T=1, M=1),
+         "large": W.config_large(T=1, M=1)}[which]
+    rob = b.robots[0]
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    rng = np.random.default_rng(2)
+    S = 2048 + 11
+    q = W.uniform_configs(rng, rob, S)
+    flag = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    H.hjcd_collide(ctx, rb, sc, soa(q, rob.dof), flag)
+    _sync()
+    fl = flag.cpu().numpy()
+    rh, sh = O.RobotHandle(rob), O.SceneHandle(b.scene)
+    checked = band = 0
+    for s in range(0, S, 3 if which != "large" else 11):
+        f, md = O.collide(rh, sh, q[s].astype(np.float64))
+        if abs(md) < 1e-5:
+            band += 1
+            continue
+        checked += 1
+        assert fl[s] == f, (s, md)
+    say(f"  checked {checked}, in contact band {band}, colliding {fl.mean():.3f}")
+    assert checked > 100
+
+
+# ---------------------------------------------------------------------------
+# selection
+# ---------------------------------------------------------------------------
+
+def test_select_exact(H, ctx):
+    import torch
+    say("case: select")
+    rng = np.random.default_rng(4)
+    counts = np.array([0, 1, 5, 64, 65, 1000, 2048, 7])
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    S, T, n, k = int(offs[-1]), len(counts), 7, 8
+    cost = (rng.integers(0, 50, size=S) * 0.125).astype(np.float32)  # ties on purpose
+    flag = rng.integers(0, 2, size=S).astype(np.uint8)
+    ep = rng.uniform(0, 2e-3, size=S).astype(np.float32)
+    eo = rng.uniform(0, 0.03, size=S).astype(np.float32)
+    q = rng.normal(size=(n, S)).astype(np.float32)
+    p = H.hjcd_params_default(top_k=k)
+    outs = dict(q=torch.zeros(T * k, n, device="cuda"), ep=torch.zeros(T * k, device="cuda"),
+                eo=torch.zeros(T * k, device="cuda"), fl=torch.zeros(T * k, dtype=torch.uint8, device="cuda"),
+                nf=torch.zeros(T, dtype=torch.int32, device="cuda"),
+                sv=torch.zeros(T, dtype=torch.uint8, device="cuda"))
+    H.hjcd_select(ctx, offs, n, n, p, cuda(q), cuda(cost), cuda(ep), cuda(eo), cuda(flag), outs["q"], outs["ep"],
+                  outs["eo"], outs["fl"], outs["nf"], outs["sv"])
+    _sync()
+    o = {kk: v.cpu().numpy() for kk, v in outs.items()}
+    for t in range(T):
+        b0, M = int(offs[t]), int(counts[t])
+        order = O.select(flag[b0:b0 + M].astype(np.int32), cost[b0:b0 + M].astype(np.float64), k)
+        assert o["nf"][t] == int((flag[b0:b0 + M] == 0).sum())
+        solved = 0
+        for r in range(k):
+            slot = t * k + r
+            m = order[r]
+            if m < 0:
+                assert o["fl"][slot] == 255 and np.isinf(o["ep"][slot])
+                continue
+            s = b0 + m
+            assert np.array_equal(o["q"][slot], q[:, s])
+            assert o["ep"][slot] == ep[s] and o["eo"][slot] == eo[s] and o["fl"][slot] == flag[s]
+            if flag[s] == 0 and ep[s] <= 1e-3 and eo[s] <= np.float32(np.pi / 180):
+                solved = 1
+        assert o["sv"][t] == solved
+
+
+# ---------------------------------------------------------------------------
+# PO-CCD and PJ-IK trajectories
+# ---------------------------------------------------------------------------
+
+def _stage_case(H, ctx, rob, T, M, seed, params, near=None):
+    """Targets = oracle FK of q*; seeds uniform (or q* + N(0, near^2))."""
+    rng = np.random.default_rng(seed)
+    qs = W.uniform_configs(rng, rob, T)
+    tg = O.targets_from_qstar(rob, qs)
+    if near is None:
+        seeds = W.uniform_configs(rng, rob, T * M)
+    else:
+        seeds = np.repeat(qs, M, axis=0) + rng.normal(scale=near, size=(T * M, rob.dof))
+        seeds = np.clip(seeds, rob.q_min, rob.q_max).astype(np.float32)
+    offs = np.arange(T + 1, dtype=np.int64) * M
+    return tg, seeds, offs
+
+
+def _run_stage(H, ctx, rob, which, tg, seeds, offs, params):
+    import torch
+    rb = H.hjcd_load_robot(ctx, rob)
+    n, S = rob.dof, int(offs[-1])
+    K = params["cd_sweeps"] if which == "cd" else params["polish_iters"]
+    p = H.params_from_dict(params, collect_stats=True)
+    q = soa(seeds, n)
+    ep = torch.zeros(S, device="cuda")
+    eo = torch.zeros(S, device="cuda")
+    cost = torch.zeros(S, device="cuda")
+    traj = torch.zeros(K + 1, n + 2, S, device="cuda")
+    fn = H.hjcd_cd if which == "cd" else H.hjcd_polish
+    fn(ctx, rb, targets_soa(tg), offs, p, q, ep, eo, cost, traj)
+    _sync()
+    st = H.hjcd_get_stats(ctx)
+    return q.cpu().numpy(), ep.cpu().numpy(), eo.cpu().numpy(), traj.cpu().numpy(), st
+
+
+def _check_stage(H, ctx, rob, which, T, M, seed, params, near=None, max_tie=0.1):
+    tg, seeds, offs = _stage_case(H, ctx, rob, T, M, seed, params, near)
+    q, ep, eo, traj, st = _run_stage(H, ctx, rob, which, tg, seeds, offs, params)
+    rh = O.RobotHandle(rob)
+    fn = O.cd if which == "cd" else O.polish
+    n = rob.dof
+    ties = 0
+    worst = 0.0
+    fails = []
+    tot_iters = 0
+    for s in range(int(offs[-1])):
+        t, m = s // M, s % M
+        r = fn(rh, tg[t].astype(np.float64), params, m, t, seeds[s].astype(np.float64))
+        ok, k, w = compare_trajectories(traj[:, :, s].T if False else traj[:, :, s], r, n)
+        tot_iters += r["stats"]["iters_run"]
+        if k < len(r["margin"]):
+            ties += 1
+        worst = max(worst, w)
+        if not ok:
+            fails.append((s, k, w))
+    frac = ties / int(offs[-1])
+    say(f"  {which}: seeds {offs[-1]}, tie-affected {ties} ({frac:.4f}), worst {worst:.2e}, "
+        f"fails {len(fails)} {fails[:5]}; gpu iters {st['cd_iters'] if which == 'cd' else st['pol_iters']}"
+        f" oracle iters {tot_iters}")
+    assert not fails, fails[:10]
+    assert frac <= max_tie
+    # self-consistency of the reported errors at the final configuration
+    assert np.all(np.isfinite(ep)) and np.all(np.isfinite(eo))
+    return traj, ties
+
+
+@pytest.mark.parametrize("name", ["panda", "ur", "random12"])
+def test_cd_trajectory(H, ctx, name):
+    say(f"case: cd trajectory {name}")
+    rob = _robots()[name]
+    _check_stage(H, ctx, rob, "cd", T=6, M=48, seed=10, params=W.default_params())
+
+
+@pytest.mark.parametrize("name", ["panda", "ur", "random12"])
+def test_polish_trajectory_near(H, ctx, name):
+    say(f"case: polish trajectory near {name}")
+    rob = _robots()[name]
+    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=11, params=W.default_params(), near=0.05)
+
+
+@pytest.mark.parametrize("name", ["panda", "random12"])
+def test_polish_trajectory_far(H, ctx, name):
+    """Uniform seeds: exercises the dogleg, single-coordinate and perturbation
+    fallbacks."""
+    say(f"case: polish trajectory far {name}")
+    rob = _robots()[name]
+    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=12, params=W.default_params(), max_tie=0.3)
+
+
+# ---------------------------------------------------------------------------
+# top-K and noisy replication between the stages
+# ---------------------------------------------------------------------------
+
+def test_resample(H, ctx):
+    import torch
+    say("case: resample")
+    rob = W.panda_like()
+    rb = H.hjcd_load_robot(ctx, rob)
+    rng = np.random.default_rng(6)
+    counts = np.array([3, 64, 100, 257])
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    S, T, n = int(offs[-1]), len(counts), rob.dof
+    q = W.uniform_configs(rng, rob, S)
+    cost = (rng.integers(0, 40, size=S) * 0.5).astype(np.float32)
+    K, B = 8, 20
+    Bp = (B // K) * K
+    p = H.params_from_dict(W.default_params(resample_K=K, resample_B=B, rng_seed=99))
+    out = torch.zeros(n, T * Bp, device="cuda")
+    H.hjcd_resample(ctx, rb, offs, p, soa(q, n), cuda(cost), out)
+    _sync()
+    g = out.cpu().numpy()
+    for t in range(T):
+        b0, M = int(offs[t]), int(counts[t])
+        order = O.select(np.zeros(M, np.int32), cost[b0:b0 + M].astype(np.float64), min(K, M))
+        for j in range(Bp):
+            kk = j % K
+            src = b0 + order[kk % M]
+            z = O.normals(99, j, t, O.ST_RESAMPLE, 0, n)
+            ref = np.clip(q[src].astype(np.float64) + 0.05 * z, rob.q_min, rob.q_max)
+            assert np.max(np.abs(g[:, t * Bp + j] - ref)) < 2e-5, (t, j)
+
+
+# ---------------------------------------------------------------------------
+# whole solve
+# ---------------------------------------------------------------------------
+
+def _solve_gpu(H, ctx, robots, batch, targets, seeds=None, params=None, target_keys=None):
+    import torch
+    rbs = [H.hjcd_load_robot(ctx, r) for r in robots]
+    sc = H.hjcd_load_scene(ctx, batch.scene.spheres, batch.scene.boxes)
+    T = len(targets)
+    params = params or batch.params
+    k = params["top_k"]
+    n_max = max(r.dof for r in robots)
+    o = dict(q=torch.zeros(T * k, n_max, device="cuda"), ep=torch.zeros(T * k, device="cuda"),
+             eo=torch.zeros(T * k, device="cuda"), fl=torch.zeros(T * k, dtype=torch.uint8, device="cuda"),
+             nf=torch.zeros(T, dtype=torch.int32, device="cuda"),
+             sv=torch.zeros(T, dtype=torch.uint8, device="cuda"))
+    p = H.params_from_dict(params)
+    H.hjcd_solve(ctx, rbs, sc, targets_soa(targets), batch.seed_offsets, p, o["q"], o["ep"], o["eo"], o["fl"],
+                 o["nf"], o["sv"], robot_of_target=batch.robot_of_target if len(robots) > 1 else None,
+                 seeds=None if seeds is None else cuda(seeds), target_keys=target_keys)
+    _sync()
+    return {kk: v.cpu().numpy() for kk, v in o.items()}
+
+
+def test_solve_tiny_matches_oracle(H, ctx):
+    say("case: solve tiny vs oracle")
+    b = W.config_tiny()
+    rob = b.robots[0]
+    tg = O.targets_from_qstar(rob, b.q_star)
+    g = _solve_gpu(H, ctx, [rob], b, tg, seeds=b.seeds)
+    ref = O.solve(rob, b.scene, tg.astype(np.float64), b.seed_offsets, b.params, seeds=b.seeds[:7].T)
+    say(f"  solved gpu {g['sv'].sum()} oracle {ref['solved'].sum()}; nfree gpu {g['nf']} oracle {ref['n_free']}")
+    assert np.sum(g["sv"] == ref["solved"]) >= b.T - 1
+    assert np.all(np.abs(g["nf"] - ref["n_free"]) <= 3)
+    for t in range(b.T):
+        if g["sv"][t] and ref["solved"][t]:
+            assert g["ep"][t] <= 1e-3 and g["eo"][t] <= np.pi / 180
+
+
+def test_solve_resample_runs(H, ctx):
+    say("case: solve with top-K resampling")
+    b = W.config_tiny()
+    rob = b.robots[0]
+    tg = O.targets_from_qstar(rob, b.q_star)
+    params = dict(b.params, resample_K=16, resample_B=40, top_k=4)
+    g = _solve_gpu(H, ctx, [rob], b, tg, seeds=b.seeds, params=params)
+    ref = O.solve(rob, b.scene, tg.astype(np.float64), b.seed_offsets, params, seeds=b.seeds[:7].T)
+    say(f"  solved gpu {g['sv'].sum()} oracle {ref['solved'].sum()}")
+    assert g["sv"].sum() >= ref["solved"].sum() - 1
+    assert np.all(g["nf"] <= 32)
+
+
+def test_uneven_batch_equals_targets_alone(H, ctx):
+    """Mixed robots and uneven seed counts in one call give, bit for bit, what
+    each target gives when solved alone with the same target key."""
+    say("case: uneven batch vs alone")
+    full = W.config_uneven(T=24, max_seeds=300)
+    tg = np.concatenate([O.targets_from_qstar(full.robots[full.robot_of_target[t]], [full.q_star[t]])
+                         for t in range(full.T)])
+    keys = np.arange(full.T, dtype=np.uint32) * 7 + 3
+    g = _solve_gpu(H, ctx, full.robots, full, tg, target_keys=cuda(keys.view(np.int32)))
+    k = full.params["top_k"]
+    n_max = full.n_max
+    for t in range(0, full.T, 3):
+        r = full.robot_of_target[t]
+        M = int(full.seed_offsets[t + 1] - full.seed_offsets[t])
+        one = W.Batch("one", [full.robots[r]], np.zeros(1, np.int32), [full.q_star[t]],
+                      np.array([0, M], np.int64), None, full.scene, full.params, 3)
+        a = _solve_gpu(H, ctx, [full.robots[r]], one, tg[t:t + 1], target_keys=cuda(keys[t:t + 1].view(np.int32)))
+        n = full.robots[r].dof
+        qa = a["q"].reshape(k, n)
+        qg = g["q"].reshape(full.T, k, n_max)[t]
+        assert np.array_equal(qa, qg[:, :n]), t
+        assert np.all(qg[:, n:] == 0)
+        assert np.array_equal(a["ep"], g["ep"].reshape(full.T, k)[t])
+        assert np.array_equal(a["fl"], g["fl"].reshape(full.T, k)[t])
+        assert a["nf"][0] == g["nf"][t] and a["sv"][0] == g["sv"][t]
+
+
+def test_full_size_sampled_parity(H, ctx):
+    """The benchmark's configuration (1,000 x 1,024 seeds, one launch per stage
+    as the solve runs them): PO-CCD then PJ-IK on every seed, and the oracle on
+    a sample of seeds one by one."""
+    import torch
+    say("case: full-size sampled parity")
+    b = W.config_batched(T=1000, M=1024, host_seeds=True)
+    rob = b.robots[0]
+    n, S = rob.dof, b.S
+    rng = np.random.default_rng(7)
+    tsel = rng.choice(b.T, size=12, replace=False)
+    tg_all = np.zeros((b.T, 7), np.float32)
+    tg_all[tsel] = O.targets_from_qstar(rob, [b.q_star[t] for t in tsel])
+    # targets the sample does not use still need sane rows
+    tg_all[:, 3] = np.where(tg_all[:, 3] == 0, 1.0, tg_all[:, 3])
+    rb = H.hjcd_load_robot(ctx, rob)
+    p = H.params_from_dict(b.params)
+    q = cuda(b.seeds)
+    K = b.params["cd_sweeps"]
+    traj = torch.zeros(K + 1, n + 2, S, device="cuda")
+    H.hjcd_cd(ctx, rb, targets_soa(tg_all), b.seed_offsets, p, q, None, None, None, traj)
+    _sync()
+    cols = np.concatenate([t * 1024 + rng.choice(1024, size=16, replace=False) for t in tsel])
+    idx = torch.as_tensor(cols).cuda()
+    tr = traj[:, :, idx].cpu().numpy()
+    q_cd = q[:, idx].cpu().numpy()
+    fails, ties = [], 0
+    for i, s in enumerate(cols):
+        t, m = s // 1024, s % 1024
+        r = O.cd(rob, tg_all[t].astype(np.float64), b.params, int(m), int(t),
+                 b.seeds[:, s].astype(np.float64))
+        ok, kk, w = compare_trajectories(tr[:, :, i], r, n)
+        ties += kk < K
+        if not ok:
+            fails.append((int(s), kk, w))
+    say(f"  cd sampled {len(cols)} seeds: ties {ties}, fails {fails[:5]}")
+    assert not fails
+    del traj
+    q_in = q.clone()
+    trp = torch.zeros(b.params["polish_iters"] + 1, n + 2, S, device="cuda")
+    H.hjcd_polish(ctx, rb, targets_soa(tg_all), b.seed_offsets, p, q, None, None, None, trp)
+    _sync()
+    trp_s = trp[:, :, idx].cpu().numpy()
+    fails, ties = [], 0
+    # PJ-IK parity from the oracle's own CD output for the seeds whose CD had no tie
+    for i, s in enumerate(cols):
+        t, m = s // 1024, s % 1024
+        r = O.cd(rob, tg_all[t].astype(np.float64), b.params, int(m), int(t), b.seeds[:, s].astype(np.float64))
+        if np.min(r["margin"]) < TAU_DEC:
+            continue
+        rp = O.polish(rob, tg_all[t].astype(np.float64), b.params, int(m), int(t), r["theta"])
+        ok, kk, w = compare_trajectories(trp_s[:, :, i], rp, n)
+        ties += kk < b.params["polish_iters"]
+        if not ok:
+            fails.append((int(s), kk, w))
+    say(f"  polish sampled: ties {ties}, fails {fails[:5]}")
+    assert not fails
+    del q_in

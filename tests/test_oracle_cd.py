@@ -140,7 +140,8 @@ def test_one_dof_orientation_step_is_exact(oracle_lib):
 
 def test_greedy_combination_and_acceptance(oracle_lib):
     """Alg. PO-CCD with the Sec. IV-A rule: best position joint and best
-    orientation joint (ties -> lower index) are both applied when they differ,
+    orientation joint (the lowest joint within tie_eps of the best score) are
+    both applied when they differ,
     else the larger step; an improvement > gamma in position or orientation
     accepts, otherwise the seed moves by N(mu, sigma^2 I) from the
     (stage=CD, iteration k) draw, clipped to the limits."""
@@ -152,7 +153,9 @@ def test_greedy_combination_and_acceptance(oracle_lib):
         th = W.uniform_configs(rng, rob, 1)[0].astype(np.float64)
         tgt = _target(O, rob, W.uniform_configs(rng, rob, 1)[0].astype(np.float64))
         c = O.cd_candidates(rob, tgt, p, th, 0)
-        jp, jo = int(np.argmin(c["sp"])), int(np.argmin(c["so"]))
+        sp, so = np.sqrt(c["sp"]), np.sqrt(c["so"])
+        jp = int(np.nonzero(sp <= sp.min() + p["tie_eps"])[0][0])
+        jo = int(np.nonzero(so <= so.min() + p["tie_eps"])[0][0])
         hat = th.copy()
         if jp != jo:
             hat[jp] += c["dp"][jp]
@@ -208,3 +211,23 @@ def test_cd_reduces_error_on_average(oracle_lib):
         e0.append(r["traj"][0, 7])
         e1.append(r["traj"][-1, 7])
     assert np.median(e1) < 0.5 * np.median(e0)
+
+
+def test_parallel_axes_tie_to_lowest_joint(oracle_lib):
+    """Joints with parallel axes give the same orientation score (a planar
+    chain: every joint turns about z); the pick is the lowest such joint, and
+    an iteration with exactly tied scores records no near-tie margin."""
+    O = oracle_lib
+    rob = _wide(W.planar_chain([0.5, 0.4, 0.3]))  # no step is clipped
+    p = W.default_params(cd_sweeps=1)
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        th = rng.uniform(-2, 2, size=3)
+        tgt = _target(O, rob, rng.uniform(-2, 2, size=3))
+        c = O.cd_candidates(rob, tgt, p, th, 0)
+        assert np.ptp(np.sqrt(c["so"])) < 1e-12
+        r = O.cd(rob, tgt, p, 0, 0, th)
+        moved = np.nonzero(np.abs(r["theta"] - th) > 0)[0]
+        if r["stats"]["n_perturb"] == 0 and moved.size:
+            jp = int(np.nonzero(np.sqrt(c["sp"]) <= np.sqrt(c["sp"]).min() + p["tie_eps"])[0][0])
+            assert set(moved.tolist()) <= {jp, 0}
