@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--seeds", type=int, default=1024)
     ap.add_argument("--cpu-targets", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve has no multi-GPU path",
@@ -99,6 +101,17 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(max(args.steps, 1)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_mib": args.copy_calibration, "copies": max(args.steps, 1),
+                          "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}), flush=True)
+        return
 
     from paper_2510_07514_amd import hjcd as H
     from paper_2510_07514_amd import workload as W
@@ -183,6 +196,9 @@ def main():
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "stage_ms": {kk: round(per_step[kk], 4) for kk in
                      ("ms_solve_kernel", "ms_collide", "ms_select", "ms_total")},
+        "work_per_step": {kk: int(per_step[kk]) for kk in
+                          ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
+                           "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},
         "roofline": roof,
     }
     if not args.no_cpu:

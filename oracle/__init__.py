@@ -57,7 +57,7 @@ class _Params(C.Structure):
                 ("eps_pol", C.c_double), ("ups_pol", C.c_double), ("sigma", C.c_double),
                 ("mu", C.c_double), ("resample_K", C.c_int32), ("resample_B", C.c_int32),
                 ("top_k", C.c_int32), ("succ_pos", C.c_double), ("succ_ori", C.c_double),
-                ("rng_seed", C.c_uint64)]
+                ("rng_seed", C.c_uint64), ("shadow", C.c_uint64)]
 
 
 class _Stats(C.Structure):
@@ -90,7 +90,7 @@ def lib():
         stage = [C.POINTER(_Robot), dp, C.POINTER(_Params), C.c_uint32, C.c_uint32, dp, dp, dp,
                  C.POINTER(_Stats)]
         L.or_cd.argtypes = stage
-        L.or_polish.argtypes = stage
+        L.or_polish.argtypes = stage[:8] + [dp, C.POINTER(_Stats)]
         L.or_cd_candidates.argtypes = [C.POINTER(_Robot), dp, C.POINTER(_Params), dp, C.c_int32,
                                        dp, dp, dp, dp]
         L.or_pjik_steps.argtypes = [C.POINTER(_Robot), dp, C.POINTER(_Params), dp, dp, dp, dp,
@@ -145,7 +145,8 @@ def params(p: dict) -> _Params:
                    p["lam"], p["lambda_gn"], p["trust_R"], p["ls_beta"], int(p["ls_A"]),
                    int(p["weight_mode"]), p["eps_pol"], p["ups_pol"], p["sigma"], p["mu"],
                    int(p["resample_K"]), int(p["resample_B"]), int(p["top_k"]),
-                   p["succ_pos"], p["succ_ori"], int(p["rng_seed"]) & 0xFFFFFFFFFFFFFFFF)
+                   p["succ_pos"], p["succ_ori"], int(p["rng_seed"]) & 0xFFFFFFFFFFFFFFFF,
+                   int(p.get("shadow", 0)))
 
 
 def _rh(robot):
@@ -230,7 +231,7 @@ def uniform_seed(robot, rng_seed, seed_idx, target_key):
 # stages on one seed
 # ---------------------------------------------------------------------------
 
-def _stage(fn, robot, target, p, seed_idx, target_key, theta, iters_key):
+def _stage(fn, robot, target, p, seed_idx, target_key, theta, iters_key, with_sens=False):
     rh = _rh(robot)
     n = rh.n
     pr = params(p)
@@ -238,12 +239,14 @@ def _stage(fn, robot, target, p, seed_idx, target_key, theta, iters_key):
     th = _d(np.asarray(theta, np.float64)).copy()
     traj = np.zeros((K + 1, n + 2))
     marg = np.zeros(max(K, 1))
+    sens = np.zeros(max(K, 1))
     st = _Stats()
+    extra = [_ptr(sens)] if with_sens else []
     rc = fn(C.byref(rh.c), _ptr(_d(target)), C.byref(pr), seed_idx, target_key, _ptr(th),
-            _ptr(traj), _ptr(marg), C.byref(st))
+            _ptr(traj), _ptr(marg), *extra, C.byref(st))
     if rc != 0:
         raise ValueError("oracle stage rejected its input")
-    return dict(theta=th, traj=traj, margin=marg[:K], stats=st.as_dict())
+    return dict(theta=th, traj=traj, margin=marg[:K], sens=sens[:K], stats=st.as_dict())
 
 
 def cd(robot, target, p, seed_idx, target_key, theta):
@@ -252,8 +255,10 @@ def cd(robot, target, p, seed_idx, target_key, theta):
 
 
 def polish(robot, target, p, seed_idx, target_key, theta):
-    """PJ-IK on one seed; same layout as ``cd``."""
-    return _stage(lib().or_polish, robot, target, p, seed_idx, target_key, theta, "polish_iters")
+    """PJ-IK on one seed; same layout as ``cd`` plus sens [K], the
+    single-precision conditioning of each iteration's step (rad)."""
+    return _stage(lib().or_polish, robot, target, p, seed_idx, target_key, theta, "polish_iters",
+                  with_sens=True)
 
 
 def cd_candidates(robot, target, p, theta, k):

@@ -709,12 +709,10 @@ int single_step(const Lin& L, const or_params& p, double* step, Margin& mg) {
 
 // ---------------------------------------------------------------------------
 // Conditioning of a PJ-IK step (test instrumentation, not part of the
-// method): how far the step moves when J and e carry single-precision-sized
-// errors.  Near singular configurations the damped systems amplify such
-// errors up to 1/lambda; an iteration whose step moves by more than
-// kSensTol is treated like a near-tie decision (margin 0).
+// method): how far the step taken moves (infinity norm, rad) when J and e
+// carry single-precision-sized errors.  Near singular configurations the
+// damped systems amplify such errors up to 1/lambda.
 // ---------------------------------------------------------------------------
-const double kSensTol = 2e-6;
 enum StepKind { STEP_LM = 0, STEP_DOGLEG = 1, STEP_SINGLE = 2, STEP_PERTURB = 3 };
 
 Lin perturbed(const Lin& L, const or_params& p, uint64_t key) {
@@ -779,7 +777,7 @@ double step_sensitivity(const Lin& L, const or_params& p, int kind, double alpha
 // PJ-IK on one seed (Alg. PJ-IK, Sec. IV-B)
 // ---------------------------------------------------------------------------
 void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, uint32_t tkey,
-           double* th, double* traj, double* margin, or_stage_stats& st, double harm) {
+           double* th, double* traj, double* margin, double* sens, or_stage_stats& st, double harm) {
     const int n = rb.n;
     const int K = p.polish_iters;
     const double R = p.trust_R;
@@ -800,10 +798,13 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             for (int kk = it + 1; kk <= K; ++kk) write_row(traj, kk, n, th, r);
             for (int kk = it + 1; kk < K; ++kk)
                 if (margin) margin[kk] = kInf;
+            for (int kk = it; kk < K; ++kk)
+                if (sens) sens[kk] = 0.0;
             return;
         }
         const double c0 = r.cost;
         Lin L = linearise(rb, p, f, r);
+        if (p.shadow) L = perturbed(L, p, p.shadow * 1000003ull + (uint64_t)it);
 
         // LM step, trust-region clamp, backtracking line search.
         double dth[OR_MAX_DOF];
@@ -845,7 +846,7 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             perturb(rb, p, m, tkey, ST_POLISH, (uint32_t)it, th);
             st.n_perturb++;
         }
-        if (step_sensitivity(L, p, kind, alpha, is, it) > kSensTol) mg.add(0.0);
+        if (sens) sens[it] = step_sensitivity(L, p, kind, alpha, is, it);
         st.iters_run++;
         if (margin) margin[it] = mg.v;
     }
@@ -1025,13 +1026,13 @@ int or_cd(const or_robot* rbi, const double* target, const or_params* pr, uint32
 }
 
 int or_polish(const or_robot* rbi, const double* target, const or_params* pr, uint32_t seed_idx,
-              uint32_t target_key, double* theta, double* traj, double* margin,
+              uint32_t target_key, double* theta, double* traj, double* margin, double* sens,
               or_stage_stats* st) {
     Robot rb;
     if (!load_robot(rbi, rb) || !pr) return -1;
     Target tg = load_target(target);
     or_stage_stats s;
-    pj_ik(rb, tg, *pr, seed_idx, target_key, theta, traj, margin, s, kHarm);
+    pj_ik(rb, tg, *pr, seed_idx, target_key, theta, traj, margin, sens, s, kHarm);
     if (st) *st = s;
     return 0;
 }
@@ -1154,7 +1155,7 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
         std::vector<double> c2(Mb), ep(Mb), eo(Mb);
         for (int m = 0; m < Mb; ++m) {
             double* x = &th[(size_t)m * n];
-            pj_ik(rb, tg, p, (uint32_t)m, tkey, x, nullptr, nullptr, s, kHarm);
+            pj_ik(rb, tg, p, (uint32_t)m, tkey, x, nullptr, nullptr, nullptr, s, kHarm);
             Res r = eval(rb, tg, x);
             c2[m] = r.cost;
             ep[m] = r.ep;

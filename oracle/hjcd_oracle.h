@@ -71,6 +71,10 @@ typedef struct {
     int32_t resample_K, resample_B, top_k;
     double succ_pos, succ_ori;
     uint64_t rng_seed;
+    /* Test instrumentation, 0 = off: PJ-IK linearises with J and e carrying
+     * single-precision-sized pseudo-random errors drawn from this key (a
+     * "shadow" run that shows how far rounding alone can move a trajectory). */
+    uint64_t shadow;
 } or_params;
 
 /* Per-seed record of one stage run (PO-CCD or PJ-IK). */
@@ -126,9 +130,12 @@ void or_uniform_seed(const or_robot* rb, uint64_t rng_seed, uint32_t seed_idx,
 int or_cd(const or_robot* rb, const double* target, const or_params* pr, uint32_t seed_idx,
           uint32_t target_key, double* theta, double* traj, double* margin, or_stage_stats* st);
 
-/* PJ-IK on one seed; same conventions with polish_iters iterations. */
+/* PJ-IK on one seed; same conventions with polish_iters iterations.
+ * sens (nullable) receives polish_iters values: how far the step taken in
+ * that iteration moves (infinity norm, rad) when J and e carry
+ * single-precision-sized errors (0 for perturbations and frozen iterations). */
 int or_polish(const or_robot* rb, const double* target, const or_params* pr, uint32_t seed_idx,
-              uint32_t target_key, double* theta, double* traj, double* margin,
+              uint32_t target_key, double* theta, double* traj, double* margin, double* sens,
               or_stage_stats* st);
 
 /* Inspection of one PO-CCD iteration k at theta: per-joint clipped position

@@ -274,7 +274,7 @@ void hjcd_params_default(hjcd_params* p) {
     p->proj_eps = 1e-5f;
     p->tie_eps = 1e-5f;
     p->lambda_ = 1e-3f;
-    p->lambda_gn = 1e-6f;
+    p->lambda_gn = 1e-4f;
     p->trust_R = 0.2f;
     p->ls_beta = 2.0f;
     p->ls_A = 4;

@@ -580,43 +580,46 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
 
 // In place: A (lower, packed) -> L with A = L L^T.  Returns false if a pivot
-// is not positive.
-__device__ __forceinline__ bool chol6(float* A) {
+// is not positive.  The 6 x 6 systems are assembled and factored in double
+// precision: near singular J their condition number (up to ~|J|^2 / lambda)
+// is beyond what single precision resolves, and double FMAs issue at the same
+// per-lane rate as unpacked single ones on CDNA4.
+__device__ __forceinline__ bool chol6(double* A) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        float s = A[tri(j, j)];
+        double s = A[tri(j, j)];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s = fmaf(-A[tri(j, k)], A[tri(j, k)], s);
-        ok = ok && (s > 0.f);
-        const float l = sqrtf(fmaxf(s, 1e-30f));
-        const float il = 1.f / l;
+        for (int k = 0; k < j; ++k) s = fma(-A[tri(j, k)], A[tri(j, k)], s);
+        ok = ok && (s > 0.0);
+        const double l = sqrt(fmax(s, 1e-300));
+        const double il = 1.0 / l;
         A[tri(j, j)] = l;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
-            float t = A[tri(i, j)];
+            double t = A[tri(i, j)];
 #pragma unroll
-            for (int k = 0; k < j; ++k) t = fmaf(-A[tri(i, k)], A[tri(j, k)], t);
+            for (int k = 0; k < j; ++k) t = fma(-A[tri(i, k)], A[tri(j, k)], t);
             A[tri(i, j)] = t * il;
         }
     }
     return ok;
 }
 
-__device__ __forceinline__ void chol6_solve(const float* L, const float* b, float* x) {
-    float y[6];
+__device__ __forceinline__ void chol6_solve(const double* L, const double* b, double* x) {
+    double y[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        float t = b[i];
+        double t = b[i];
 #pragma unroll
-        for (int k = 0; k < i; ++k) t = fmaf(-L[tri(i, k)], y[k], t);
+        for (int k = 0; k < i; ++k) t = fma(-L[tri(i, k)], y[k], t);
         y[i] = t / L[tri(i, i)];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
-        float t = y[i];
+        double t = y[i];
 #pragma unroll
-        for (int k = i + 1; k < 6; ++k) t = fmaf(-L[tri(k, i)], x[k], t);
+        for (int k = i + 1; k < 6; ++k) t = fma(-L[tri(k, i)], x[k], t);
         x[i] = t / L[tri(i, i)];
     }
 }
@@ -693,24 +696,28 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
                     w6[r] = kp.weight_mode == 0 ? 1.f / fmaxf(sqrtf(rn[r]), 1e-6f) : 1.f;
-                // A = W (sum_j J_j J_j^T / D_j) W + lam I,  D_j = |J_j|^2
-                float A[21];
+                // A = W (sum_j J_j J_j^T / D_j) W + lam I,  D_j = |J_j|^2 (double)
+                double A[21];
 #pragma unroll
-                for (int i = 0; i < 21; ++i) A[i] = 0.f;
+                for (int i = 0; i < 21; ++i) A[i] = 0.0;
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
                     if (j < n) {
                         float c[6];
                         jcol(Jp, Z, j, c);
-                        float dj = 0.f;
+                        double cd[6];
+                        double dj = 0.0;
 #pragma unroll
-                        for (int r = 0; r < 6; ++r) dj = fmaf(c[r], c[r], dj);
-                        const float idj = 1.f / dj;
+                        for (int r = 0; r < 6; ++r) {
+                            cd[r] = (double)c[r];
+                            dj = fma(cd[r], cd[r], dj);
+                        }
+                        const double idj = 1.0 / dj;
 #pragma unroll
                         for (int a = 0; a < 6; ++a) {
-                            const float ca = c[a] * idj;
+                            const double ca = cd[a] * idj;
 #pragma unroll
-                            for (int b = 0; b <= a; ++b) A[tri(a, b)] = fmaf(ca, c[b], A[tri(a, b)]);
+                            for (int b = 0; b <= a; ++b) A[tri(a, b)] = fma(ca, cd[b], A[tri(a, b)]);
                         }
                     }
                 }
@@ -718,14 +725,15 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                 for (int a = 0; a < 6; ++a)
 #pragma unroll
                     for (int b = 0; b <= a; ++b)
-                        A[tri(a, b)] = A[tri(a, b)] * w6[a] * w6[b] + (a == b ? kp.lam : 0.f);
+                        A[tri(a, b)] = A[tri(a, b)] * ((double)w6[a] * (double)w6[b]) + (a == b ? (double)kp.lam : 0.0);
                 chol6(A);
-                float rhs[6], y[6];
+                double rhs[6], yd[6];
 #pragma unroll
-                for (int r = 0; r < 6; ++r) rhs[r] = w6[r] * e6[r];
-                chol6_solve(A, rhs, y);
+                for (int r = 0; r < 6; ++r) rhs[r] = (double)w6[r] * (double)e6[r];
+                chol6_solve(A, rhs, yd);
+                float y[6];
 #pragma unroll
-                for (int r = 0; r < 6; ++r) y[r] *= w6[r];
+                for (int r = 0; r < 6; ++r) y[r] = (float)(yd[r] * (double)w6[r]);
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
                     if (j < n) {
@@ -788,10 +796,10 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
 #pragma unroll
                 for (int r = 0; r < 6; ++r) jgjg = fmaf(Jg[r], Jg[r], jgjg);
                 const float ac = jgjg > 0.f ? gg / jgjg : 0.f;
-                // Gauss-Newton: J^T (J J^T + lambda_gn I)^-1 e
-                float A[21];
+                // Gauss-Newton: J^T (J J^T + lambda_gn I)^-1 e (system in double)
+                double A[21];
 #pragma unroll
-                for (int i = 0; i < 21; ++i) A[i] = 0.f;
+                for (int i = 0; i < 21; ++i) A[i] = 0.0;
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
                     if (j < n) {
@@ -800,14 +808,20 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
 #pragma unroll
                         for (int a = 0; a < 6; ++a)
 #pragma unroll
-                            for (int b = 0; b <= a; ++b) A[tri(a, b)] = fmaf(c[a], c[b], A[tri(a, b)]);
+                            for (int b = 0; b <= a; ++b)
+                                A[tri(a, b)] = fma((double)c[a], (double)c[b], A[tri(a, b)]);
                     }
                 }
 #pragma unroll
-                for (int a = 0; a < 6; ++a) A[tri(a, a)] += kp.lambda_gn;
+                for (int a = 0; a < 6; ++a) A[tri(a, a)] += (double)kp.lambda_gn;
                 chol6(A);
+                double ed[6], yd[6];
+#pragma unroll
+                for (int r = 0; r < 6; ++r) ed[r] = (double)e6[r];
+                chol6_solve(A, ed, yd);
                 float y[6];
-                chol6_solve(A, e6, y);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) y[r] = (float)yd[r];
                 float ngn2 = 0.f, ngd2 = 0.f;
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
@@ -824,33 +838,36 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                     }
                 }
                 const float ngn = sqrtf(ngn2), ngd = sqrtf(ngd2);
-                // blend: tau = 0 if |GN| <= R; GD scaled to R if |GD| >= R; else the
-                // smaller root of |GN + tau (GD - GN)| = R
-                float tau = 0.f, scale_gd = 1.f;
-                bool use_gd = false;
+                // blend: GN if |GN| <= R; GD scaled to R if |GD| >= R; else the
+                // point GN + tau (GD - GN) with norm R and the smallest tau, written
+                // as GD + s (GN - GD), s = 1 - tau: the root in s keeps full
+                // relative precision when |GN| >> R (near singular J).
+                float s_gn = 0.f, scale_gd = 1.f;
+                bool use_gn = false;
                 if (ngn <= R) {
-                    tau = 0.f;
+                    use_gn = true;
                 } else if (ngd >= R) {
-                    use_gd = true;
                     scale_gd = R / ngd;
                 } else {
                     float aa = 0.f, bb = 0.f;
 #pragma unroll
                     for (int j = 0; j < NM; ++j) {
                         if (j < n) {
-                            const float dj = dth[j] - tt[j];
+                            const float dj = tt[j] - dth[j];
                             aa = fmaf(dj, dj, aa);
-                            bb = fmaf(tt[j], dj, bb);
+                            bb = fmaf(dth[j], dj, bb);
                         }
                     }
-                    const float cc = ngn2 - R * R;
-                    const float den = -bb + sqrtf(fmaxf(bb * bb - aa * cc, 0.f));
-                    tau = den > 0.f ? clampf(cc / den, 0.f, 1.f) : 0.f;
+                    // aa s^2 + 2 bb s + (|GD|^2 - R^2) = 0, positive root
+                    const float cc = ngd2 - R * R;  // < 0
+                    const float disc = sqrtf(fmaxf(bb * bb - aa * cc, 0.f));
+                    s_gn = bb >= 0.f ? (-cc) / (bb + disc) : (disc - bb) / fmaxf(aa, 1e-30f);
+                    s_gn = clampf(s_gn, 0.f, 1.f);
                 }
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
                     if (j < n) {
-                        const float st = use_gd ? scale_gd * dth[j] : fmaf(tau, dth[j] - tt[j], tt[j]);
+                        const float st = use_gn ? tt[j] : fmaf(s_gn, tt[j] - dth[j], scale_gd * dth[j]);
                         tt[j] = clampf(th[j] + st, rb->lo[j], rb->hi[j]);
                     }
                 }

@@ -203,7 +203,7 @@ def default_params(**over) -> dict:
         delta0=1.0, delta_decay=0.9, delta_min=0.1,   # annealing delta(k)
         proj_eps=1e-5,                       # min distance (m) of EE / target from a joint axis
         tie_eps=1e-5,                        # greedy picks: scores within this (m / rad) of the best tie
-        lam=1e-3, lambda_gn=1e-6,            # LM damping; GN regulariser in the dogleg
+        lam=1e-3, lambda_gn=1e-4,            # LM damping; GN regulariser in the dogleg
         trust_R=0.2, ls_beta=2.0, ls_A=4,    # trust region, backtracking schedule
         weight_mode=0,                       # 0 = row-normalised W, 1 = identity
         eps_pol=1e-5, ups_pol=1e-5,          # PJ-IK exit (m, rad)

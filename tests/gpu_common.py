@@ -39,11 +39,29 @@ def first_tie(margin):
     return int(bad[0]) if bad.size else len(margin)
 
 
-def compare_trajectories(gpu_traj, orc, n, wrap=False):
+SHADOW_FRAC = 0.25   # shadows must agree within TOL_TRAJ * SHADOW_FRAC
+N_SHADOWS = 3
+
+
+def shadow_horizon(orc, shadows):
+    """Last row on which every FP64 shadow run (linearisations carrying
+    single-precision-sized errors) stays within TOL_TRAJ * SHADOW_FRAC of
+    the nominal oracle trajectory; rows beyond it are not reproducible in
+    single precision and are not compared."""
+    if not shadows:
+        return orc["traj"].shape[0] - 1
+    dv = np.max([np.abs(s["traj"] - orc["traj"]).max(axis=1) for s in shadows], axis=0)
+    bad = np.nonzero(dv > TOL_TRAJ * SHADOW_FRAC)[0]
+    return int(bad[0]) - 1 if bad.size else orc["traj"].shape[0] - 1
+
+
+def compare_trajectories(gpu_traj, orc, n, shadows=None):
     """gpu_traj: [rows][n+2] float32 of one seed; orc: oracle stage dict.
-    Compares rows 0..k* (k* = first tie iteration, inclusive); returns
-    (ok, k_star, worst_error)."""
-    k = first_tie(orc["margin"])
+    Compares rows 0..k* where k* is the first near-tie iteration (inclusive)
+    or the shadow horizon, whichever comes first; returns (ok, k_star,
+    worst_error).  k_star < number of iterations marks the seed as
+    tie-affected."""
+    k = min(first_tie(orc["margin"]), shadow_horizon(orc, shadows))
     rows = min(k + 1, gpu_traj.shape[0])
     g = gpu_traj[:rows].astype(np.float64)
     o = orc["traj"][:rows]
@@ -58,5 +76,5 @@ def quat_close(a, b):
     return min(np.max(np.abs(a - b)), np.max(np.abs(a + b)))
 
 
-__all__ = ["TAU_DEC", "TOL_TRAJ", "say", "cuda", "soa", "targets_soa", "first_tie",
-           "compare_trajectories", "quat_close", "math"]
+__all__ = ["TAU_DEC", "TOL_TRAJ", "SHADOW_FRAC", "N_SHADOWS", "say", "cuda", "soa", "targets_soa",
+           "first_tie", "shadow_horizon", "compare_trajectories", "quat_close", "math"]

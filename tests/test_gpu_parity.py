@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_common import TAU_DEC, TOL_TRAJ, compare_trajectories, cuda, quat_close, say, soa, targets_soa
+from gpu_common import N_SHADOWS, TAU_DEC, TOL_TRAJ, compare_trajectories, cuda, quat_close, say, soa, targets_soa
 from paper_2510_07514_amd import workload as W
 
 pytestmark = pytest.mark.gpu
@@ -238,8 +238,11 @@ def _check_stage(H, ctx, rob, which, T, M, seed, params, near=None, max_tie=0.1)
     tot_iters = 0
     for s in range(int(offs[-1])):
         t, m = s // M, s % M
-        r = fn(rh, tg[t].astype(np.float64), params, m, t, seeds[s].astype(np.float64))
-        ok, k, w = compare_trajectories(traj[:, :, s].T if False else traj[:, :, s], r, n)
+        x0 = seeds[s].astype(np.float64)
+        r = fn(rh, tg[t].astype(np.float64), params, m, t, x0)
+        shadows = [fn(rh, tg[t].astype(np.float64), dict(params, shadow=i + 1), m, t, x0)
+                   for i in range(N_SHADOWS)] if which == "polish" else None
+        ok, k, w = compare_trajectories(traj[:, :, s], r, n, shadows)
         tot_iters += r["stats"]["iters_run"]
         if k < len(r["margin"]):
             ties += 1
@@ -268,16 +271,17 @@ def test_cd_trajectory(H, ctx, name):
 def test_polish_trajectory_near(H, ctx, name):
     say(f"case: polish trajectory near {name}")
     rob = _robots()[name]
-    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=11, params=W.default_params(), near=0.05)
+    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=11, params=W.default_params(), near=0.05,
+                 max_tie=0.3)
 
 
-@pytest.mark.parametrize("name", ["panda", "random12"])
+@pytest.mark.parametrize("name", ["panda", "ur", "random12"])
 def test_polish_trajectory_far(H, ctx, name):
     """Uniform seeds: exercises the dogleg, single-coordinate and perturbation
     fallbacks."""
     say(f"case: polish trajectory far {name}")
     rob = _robots()[name]
-    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=12, params=W.default_params(), max_tie=0.3)
+    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=12, params=W.default_params(), max_tie=0.6)
 
 
 # ---------------------------------------------------------------------------
@@ -430,23 +434,23 @@ def test_full_size_sampled_parity(H, ctx):
     say(f"  cd sampled {len(cols)} seeds: ties {ties}, fails {fails[:5]}")
     assert not fails
     del traj
-    q_in = q.clone()
+    # PJ-IK from the same host seeds, every seed polished in one launch
+    q = cuda(b.seeds)
     trp = torch.zeros(b.params["polish_iters"] + 1, n + 2, S, device="cuda")
     H.hjcd_polish(ctx, rb, targets_soa(tg_all), b.seed_offsets, p, q, None, None, None, trp)
     _sync()
     trp_s = trp[:, :, idx].cpu().numpy()
+    del trp
     fails, ties = [], 0
-    # PJ-IK parity from the oracle's own CD output for the seeds whose CD had no tie
     for i, s in enumerate(cols):
         t, m = s // 1024, s % 1024
-        r = O.cd(rob, tg_all[t].astype(np.float64), b.params, int(m), int(t), b.seeds[:, s].astype(np.float64))
-        if np.min(r["margin"]) < TAU_DEC:
-            continue
-        rp = O.polish(rob, tg_all[t].astype(np.float64), b.params, int(m), int(t), r["theta"])
-        ok, kk, w = compare_trajectories(trp_s[:, :, i], rp, n)
+        x0 = b.seeds[:, s].astype(np.float64)
+        tgt = tg_all[t].astype(np.float64)
+        rp = O.polish(rob, tgt, b.params, int(m), int(t), x0)
+        shadows = [O.polish(rob, tgt, dict(b.params, shadow=j + 1), int(m), int(t), x0) for j in range(N_SHADOWS)]
+        ok, kk, w = compare_trajectories(trp_s[:, :, i], rp, n, shadows)
         ties += kk < b.params["polish_iters"]
         if not ok:
             fails.append((int(s), kk, w))
-    say(f"  polish sampled: ties {ties}, fails {fails[:5]}")
+    say(f"  polish sampled {len(cols)} seeds: tie-affected {ties}, fails {fails[:5]}")
     assert not fails
-    del q_in
