@@ -64,6 +64,35 @@ def algorithmic_flops(n, st, modified=True, tool_rot=False):
             + (st["cd_perturb"] + st["pol_perturb"]) * u["perturb"] + st["seeds"] * u["seed"])
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_batched_panda_1000x1024_traffic.txt")
+KERNEL_SOURCES = ("hjcd_device.hpp", "hjcd_launch.hpp", "hjcd_solve_inst.hip")
+
+
+def kernel_sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_07514_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_solve launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (scaled by the plain-copy calibration), or None when the
+    kernel's sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != kernel_sources_sha():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
 def cpu_baseline(batch, n_targets):
     """FP64 oracle on the first n_targets targets of the batch (all their
     seeds, uniform Philox seeds like the GPU run), all host cores."""
@@ -83,6 +112,55 @@ def cpu_baseline(batch, n_targets):
             "solved": solved, "seconds": dt}
 
 
+def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
+    """Poisson request streams served by the continuous-batching server and
+    by the plain one-request-per-launch server (same requests, same keys)."""
+    from paper_2510_07514_amd import workload as W
+    out = []
+    for rate in rates:
+        s = W.serving_stream(float(rate), duration)
+        rob, scene = s["robot"], s["scene"]
+        rb = H.hjcd_load_robot(ctx, rob)
+        sc = H.hjcd_load_scene(ctx, scene.spheres, scene.boxes)
+        n_req = len(s["arrival"])
+        # target poses = FK(q*) by the library's FK kernel
+        qs = np.concatenate(s["q_star"]).astype(np.float32)
+        qd = torch.as_tensor(np.ascontiguousarray(qs.T)).cuda()
+        pose = torch.zeros(7, qs.shape[0], device="cuda")
+        H.hjcd_fk(ctx, rb, qd, pose, None)
+        torch.cuda.synchronize()
+        poses = pose.cpu().numpy().T.copy()
+        offs = np.concatenate([[0], np.cumsum(s["n_targets"])])
+        params = H.params_from_dict(s["params"])
+        row = {"rate_req_s": rate, "requests": int(n_req), "targets": int(offs[-1]),
+               "mean_seeds_per_target": round(float(np.mean(s["seeds_per_target"])), 1)}
+        for mode, name in ((H.HJCD_SERVE_BATCHED, "served"), (H.HJCD_SERVE_PLAIN, "plain")):
+            m = n_req if mode == H.HJCD_SERVE_BATCHED else min(n_req, plain_cap)
+            srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk,
+                                       max_queue=n_req + 1)
+            for i in range(m):
+                H.hjcd_server_submit(srv, poses[offs[i]:offs[i + 1]], int(s["seeds_per_target"][i]), int(offs[i]),
+                                     float(s["arrival"][i]))
+            t0 = time.perf_counter()
+            H.hjcd_server_start(srv)
+            H.hjcd_server_wait(srv, 600.0)
+            wall = time.perf_counter() - t0
+            st = H.hjcd_server_get_stats(srv)
+            srv.close()
+            row[name] = {"requests": m, "solves_per_s": round(st["solves_per_s"], 1),
+                         "p50_latency_ms": round(st["p50_latency_ms"], 3),
+                         "p99_latency_ms": round(st["p99_latency_ms"], 3),
+                         "targets_solved": int(st["targets_solved"]), "targets_done": int(st["targets_done"]),
+                         "chunks": int(st["chunks"]), "mean_resident_slots": round(st["mean_resident_slots"], 1),
+                         "wall_s": round(wall, 3)}
+            log(f"serving {name} at {rate} req/s: {row[name]}")
+        row["speedup_solves_per_s"] = round(row["served"]["solves_per_s"] / max(row["plain"]["solves_per_s"], 1e-9), 2)
+        out.append(row)
+        rb.close()
+        sc.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,8 +168,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--targets", type=int, default=1000)
     ap.add_argument("--seeds", type=int, default=1024)
-    ap.add_argument("--cpu-targets", type=int, default=16)
+    ap.add_argument("--cpu-targets", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", default="2000,10000,50000")
+    ap.add_argument("--serve-duration", type=float, default=0.25, help="seconds of each request stream")
+    ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
+    ap.add_argument("--serve-chunk", type=int, default=4, help="iterations per serving chunk")
+    ap.add_argument("--plain-cap", type=int, default=4000, help="requests of each stream the plain server runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -172,7 +256,7 @@ def main():
     achieved = flops / (kavg * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": "k_solve (fused PO-CCD + PJ-IK)", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
+            "traffic": measured_traffic(), "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
     line = {
         "metric": "collision-free IK solves/s at 1mm/1deg",
         "value": round(value, 1),
@@ -201,6 +285,14 @@ def main():
                            "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},
         "roofline": roof,
     }
+    if not args.no_serve:
+        def log(msg):
+            print(msg, file=sys.stderr, flush=True)
+        rates = [int(x) for x in args.serve_rates.split(",") if x]
+        line["serving"] = {"workload": "poisson_panda_1-16_targets_32-1024_seeds", "chunk_iters": args.serve_chunk,
+                           "max_slots": args.serve_slots, "duration_s": args.serve_duration,
+                           "rates": serving(H, ctx, torch, rates, args.serve_duration, args.serve_slots,
+                                            args.serve_chunk, args.plain_cap, log)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_targets, T))
     print(json.dumps(line), flush=True)

@@ -233,6 +233,87 @@ hjcd_status hjcd_solve(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots,
  * the stream that call used). */
 hjcd_status hjcd_get_stats(hjcd_ctx ctx, hjcd_stats* out);
 
+/* ---- serving ----------------------------------------------------------------
+ * A request loop over one robot and scene.  Requests (a few target poses with
+ * a seed budget each) are submitted with a scheduled arrival time on the
+ * server clock; a scheduler thread admits arrived requests as long as their
+ * seeds fit in the resident slot pool (sized from a device-memory budget),
+ * keeps every admitted seed's state resident in device memory, and advances
+ * all of them together in chunks of `chunk_iters` iterations (continuous
+ * batching: requests join and leave between chunks).  A target retires at the
+ * end of the first chunk in which one of its PJ-IK-converged seeds is
+ * collision free within succ_pos / succ_ori (its best such seed by (cost,
+ * index)); otherwise it returns its best seed by (collision, cost, index)
+ * after the last PJ-IK iteration.  Every decision is taken at request-local
+ * iteration counts and the random draws are keyed by the request tag, so a
+ * request's result does not depend on what else is resident.
+ * HJCD_SERVE_PLAIN runs the same stream one request at a time with
+ * hjcd_solve (no cross-request batching, no early retirement), for
+ * comparison; its scheduler thread calls hjcd_solve on the server's context,
+ * which must not be used by other threads meanwhile.  Times are seconds since
+ * hjcd_server_start.  Memory: the batched server allocates its slot pool
+ * ((dof + 3) floats + 9 bytes per slot) and target table at create; nothing
+ * is allocated per request on the device. */
+typedef struct hjcd_server_s* hjcd_server;
+
+typedef enum { HJCD_SERVE_BATCHED = 0, HJCD_SERVE_PLAIN = 1 } hjcd_serve_mode;
+
+typedef struct {
+    int32_t mode;          /* hjcd_serve_mode */
+    int64_t max_slots;     /* resident seed slots (rounded up to 64); 0 = from hbm_budget */
+    size_t hbm_budget;     /* bytes for resident state when max_slots = 0 (0 = a quarter of free
+                              memory, at most 8 GiB) */
+    int32_t max_targets;   /* resident targets (0 = slots / 32, between 64 and 2^20) */
+    int32_t chunk_iters;   /* iterations per chunk (>= 1) */
+    int32_t max_queue;     /* pending requests accepted before submit returns HJCD_E_BUSY */
+} hjcd_server_config;
+
+typedef struct {
+    int64_t request_id;
+    uint64_t tag;
+    int32_t n_targets;
+    int32_t n_solved;      /* targets solved (collision free within tolerance) */
+    double arrival_s, admitted_s, done_s;
+} hjcd_request_info;
+
+typedef struct {
+    int64_t submitted, admitted, completed, chunks;
+    int64_t targets_solved, targets_done;
+    int64_t max_slots, resident_slots_peak;
+    double mean_resident_slots;  /* over chunks */
+    double p50_latency_ms, p99_latency_ms;  /* done - arrival over completed requests */
+    double first_arrival_s, last_done_s;
+    double solves_per_s;   /* targets_solved / (last_done - first_arrival) */
+} hjcd_server_stats;
+
+hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene /* nullable */,
+                               const hjcd_params* params, const hjcd_server_config* config,
+                               hjcd_server* out);
+/* Set the server clock to 0 and start the scheduler thread. */
+hjcd_status hjcd_server_start(hjcd_server srv);
+/* Queue one request: targets host float [n_targets][7] (px py pz qw qx qy qz),
+ * seeds_per_target >= 1, tag keys the random draws (target i of the request
+ * uses Philox target key (uint32)(tag + i), the key hjcd_solve gives target
+ * tag + i by default; seed m of it starts at the uniform draw of seed index
+ * m), arrival_s on the server
+ * clock (<= now: arrives immediately).  HJCD_E_NOMEM if it can never fit,
+ * HJCD_E_BUSY if max_queue requests are pending.  Thread safe. */
+hjcd_status hjcd_server_submit(hjcd_server srv, int32_t n_targets, const float* targets,
+                               int32_t seeds_per_target, uint64_t tag, double arrival_s,
+                               int64_t* request_id);
+/* Completed requests not yet reported (up to max), oldest first. */
+hjcd_status hjcd_server_poll(hjcd_server srv, int32_t max, hjcd_request_info* out, int32_t* n_out);
+/* Per-target results of a completed request (host arrays, n_targets rows):
+ * q [n_targets][dof], err_p, err_o, flag (0 free, 1 colliding, 255 none).
+ * The request's record is released afterwards. */
+hjcd_status hjcd_server_result(hjcd_server srv, int64_t request_id, float* q, float* err_p, float* err_o,
+                               uint8_t* flag);
+/* Block until every submitted request has completed or timeout_s elapsed
+ * (HJCD_E_BUSY on timeout). */
+hjcd_status hjcd_server_wait(hjcd_server srv, double timeout_s);
+hjcd_status hjcd_server_get_stats(hjcd_server srv, hjcd_server_stats* out);
+void hjcd_server_destroy(hjcd_server srv);
+
 /* Diagnostics: raw Philox4x32-10 words, out[4*i .. 4*i+3] = Philox(ctr =
  * (ctr0 + i, ctr1, ctr2, ctr3), key = (key0, key1)) for i < count, device
  * uint32 [4*count]. */

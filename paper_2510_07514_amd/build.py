@@ -29,15 +29,16 @@ COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
 
 def _units():
     units = [("hjcd_kernels.o", "hjcd_kernels.hip", []),
-             ("hjcd_api.o", "hjcd_api.cpp", ["-x", "hip"])]
+             ("hjcd_api.o", "hjcd_api.cpp", ["-x", "hip"]),
+             ("hjcd_server.o", "hjcd_server.cpp", ["-x", "hip"])]
     for nm in NM_BUCKETS:
         units.append((f"hjcd_solve_nm{nm}.o", "hjcd_solve_inst.hip", [f"-DHJCD_NM={nm}"]))
     return units
 
 
-def _compile(unit, verbose):
+def _compile(unit, verbose, flags, build_dir):
     obj, src, extra = unit
-    cmd = [HIPCC] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, obj)]
+    cmd = [HIPCC] + COMMON + flags + extra + ["-c", os.path.join(CSRC, src), "-o", os.path.join(build_dir, obj)]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,21 +47,24 @@ def _compile(unit, verbose):
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every unit and link libhjcd.so; returns the library path."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, flags=(), lib_path: str = LIB,
+          build_dir: str = BUILD) -> str:
+    """Compile every unit (extra hipcc `flags`, e.g. -DHJCD_WAVES_PER_EU=3) and
+    link the library at `lib_path`; returns the library path."""
+    os.makedirs(build_dir, exist_ok=True)
     units = _units()
+    flags = list(flags)
     jobs = jobs or min(len(units), max(1, min(os.cpu_count() or 4, 8)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda u: _compile(u, verbose), units))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda u: _compile(u, verbose, flags, build_dir), units))
+    tmp = lib_path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + \
-          [os.path.join(BUILD, o) for o in objs]
+          [os.path.join(build_dir, o) for o in objs] + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

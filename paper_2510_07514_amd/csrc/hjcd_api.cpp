@@ -11,14 +11,17 @@
 #include <vector>
 
 #include "../../include/hjcd.h"
+#include "hjcd_internal.hpp"
 #include "hjcd_launch.hpp"
 #include "hjcd_tables.hpp"
 
 using namespace hjcd;
 
-namespace {
+namespace hjcd {
 
+namespace {
 thread_local std::string g_err;
+}  // namespace
 
 hjcd_status fail(hjcd_status s, const char* fmt, ...) {
     char buf[512];
@@ -30,51 +33,7 @@ hjcd_status fail(hjcd_status s, const char* fmt, ...) {
     return s;
 }
 
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(HJCD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-};
-
-}  // namespace
-
-struct hjcd_ctx_s {
-    int device = 0;
-    DevBuf voffs, voffs2, coffs, tperm, tkeys_dummy, q_work, q_work2, ep, eo, cost, flag, rank, counters;
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
-    size_t pinned_used = 0;
-    hipEvent_t staging_ev = nullptr;
-    // stats
-    static constexpr int kEv = 16;
-    hipEvent_t ev[kEv] = {};
-    int ev_used = 0;
-    int ev_stage[kEv] = {};
-    bool stats_pending = false;
-    hjcd_stats stats{};
-    hipStream_t stats_stream = nullptr;
-};
-
-struct hjcd_robot_s {
-    hjcd_ctx ctx = nullptr;
-    DevRobot host;
-    DevRobot* dev = nullptr;
-    int n = 0;
-};
-
-struct hjcd_scene_s {
-    hjcd_ctx ctx = nullptr;
-    float* sph = nullptr;
-    int32_t n_sph = 0;
-    float* box = nullptr;
-    int32_t n_box = 0;
-};
+}  // namespace hjcd
 
 namespace {
 
@@ -139,7 +98,9 @@ size_t staging_bytes(std::initializer_list<size_t> parts) {
 
 bool finite_f(float x) { return std::isfinite(x); }
 
-hjcd_status check_params(const hjcd_params* p) {
+}  // namespace
+
+hjcd_status hjcd::check_params(const hjcd_params* p) {
     if (!p) return fail(HJCD_E_INVALID, "params is NULL");
     if (p->cd_sweeps < 0 || p->cd_sweeps > (1 << 20) || p->polish_iters < 0 || p->polish_iters > (1 << 20))
         return fail(HJCD_E_INVALID, "iteration counts must be in [0, 2^20]");
@@ -163,7 +124,7 @@ hjcd_status check_params(const hjcd_params* p) {
     return HJCD_OK;
 }
 
-KernelParams kparams(const hjcd_params& p) {
+KernelParams hjcd::kparams(const hjcd_params& p) {
     KernelParams k;
     k.cd_sweeps = p.cd_sweeps;
     k.polish_iters = p.polish_iters;
@@ -188,6 +149,8 @@ KernelParams kparams(const hjcd_params& p) {
     k.seed = p.rng_seed;
     return k;
 }
+
+namespace {
 
 hjcd_status check_offsets(int32_t T, const int64_t* offs) {
     if (T < 0) return fail(HJCD_E_INVALID, "T must be >= 0");

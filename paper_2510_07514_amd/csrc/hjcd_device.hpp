@@ -399,18 +399,21 @@ __device__ __forceinline__ void write_traj(float* __restrict__ traj, int n, int6
 }
 
 // ----------------------------------------------------------------------------
-// PO-CCD (Alg. PO-CCD, Sec. III, Sec. IV-A) on one seed.  `live` is false
-// for padding lanes; they run the uniform control flow with no effect.
+// PO-CCD (Alg. PO-CCD, Sec. III, Sec. IV-A) on one seed, iterations
+// [k0, k1).  `live` is false for padding lanes; they run the uniform control
+// flow with no effect.  `frozen` carries the exit state across calls (a
+// fresh seed starts with frozen = !live).  out_err is the residual at the
+// configuration the last iteration produced.
 // ----------------------------------------------------------------------------
 template <int NM>
 __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
-                       uint32_t m, uint32_t tkey, float* th, bool live, Counters& cnt,
-                       float* __restrict__ traj, int64_t S, int64_t s, Err& out_err) {
-    bool frozen = !live;
+                                       uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
+                                       Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
+                                       int k1, Err& out_err) {
     float last_ep = 0.f, last_phi = 0.f;
     V3 P[NM], Z[NM];
-    float delta = kp.delta0;
-    for (int k = 0; k < kp.cd_sweeps; ++k) {
+    float delta = kp.delta0 * powf(kp.delta_decay, (float)k0);
+    for (int k = k0; k < k1; ++k) {
         if (wave_all(frozen) && !traj) break;
         if (!frozen) {
             Frame ee;
@@ -571,7 +574,7 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
     V3 Pd[1], Zd[1];
     fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
     out_err = residual(ee, tg);
-    if (live) write_traj<NM>(traj, n, S, s, kp.cd_sweeps, th, sqrtf(out_err.ep2), out_err.phi);
+    if (live) write_traj<NM>(traj, n, S, s, k1, th, sqrtf(out_err.ep2), out_err.phi);
 }
 
 // ----------------------------------------------------------------------------
@@ -650,14 +653,14 @@ __device__ __forceinline__ float trial_cost(const DevRobot* __restrict__ rb, int
 // ----------------------------------------------------------------------------
 template <int NM>
 __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
-                      uint32_t m, uint32_t tkey, float* th, bool live, Counters& cnt,
-                      float* __restrict__ traj, int64_t S, int64_t s, Err& out_err) {
-    bool frozen = !live;
+                                      uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
+                                      Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
+                                      int k1, Err& out_err) {
     float last_ep = 0.f, last_phi = 0.f;
     V3 Jp[NM], Z[NM];
     float dth[NM], tt[NM];
     const float R = kp.trust_R;
-    for (int it = 0; it < kp.polish_iters; ++it) {
+    for (int it = k0; it < k1; ++it) {
         if (wave_all(frozen) && !traj) break;
         bool done = true;  // lane needs no further fallback this iteration
         float c0 = 0.f;
@@ -939,7 +942,7 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
     V3 Pd[1], Zd[1];
     fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
     out_err = residual(ee, tg);
-    if (live) write_traj<NM>(traj, n, S, s, kp.polish_iters, th, sqrtf(out_err.ep2), out_err.phi);
+    if (live) write_traj<NM>(traj, n, S, s, k1, th, sqrtf(out_err.ep2), out_err.phi);
 }
 
 // ----------------------------------------------------------------------------

@@ -1,0 +1,65 @@
+// Private declarations shared by the C ABI (hjcd_api.cpp) and the serving
+// loop (hjcd_server.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/hjcd.h"
+#include "hjcd_launch.hpp"
+#include "hjcd_tables.hpp"
+
+namespace hjcd {
+
+// Thread-local error text behind hjcd_last_error(); returns s.
+hjcd_status fail(hjcd_status s, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::hjcd::fail(HJCD_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+hjcd_status check_params(const hjcd_params* p);
+KernelParams kparams(const hjcd_params& p);
+
+}  // namespace hjcd
+
+struct hjcd_ctx_s {
+    int device = 0;
+    hjcd::DevBuf voffs, voffs2, coffs, tperm, tkeys_dummy, q_work, q_work2, ep, eo, cost, flag, rank, counters;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    size_t pinned_used = 0;
+    hipEvent_t staging_ev = nullptr;
+    // stats
+    static constexpr int kEv = 16;
+    hipEvent_t ev[kEv] = {};
+    int ev_used = 0;
+    int ev_stage[kEv] = {};
+    bool stats_pending = false;
+    hjcd_stats stats{};
+    hipStream_t stats_stream = nullptr;
+};
+
+struct hjcd_robot_s {
+    hjcd_ctx ctx = nullptr;
+    hjcd::DevRobot host;
+    hjcd::DevRobot* dev = nullptr;
+    int n = 0;
+};
+
+struct hjcd_scene_s {
+    hjcd_ctx ctx = nullptr;
+    float* sph = nullptr;
+    int32_t n_sph = 0;
+    float* box = nullptr;
+    int32_t n_box = 0;
+};

@@ -79,24 +79,25 @@ __device__ __forceinline__ float box_d2(V3 c, const float* __restrict__ b) {
     return fmaf(ex, ex, fmaf(ey, ey, ez * ez));
 }
 
-__global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * 64 + lane;
-    const bool live = s < a.S;
-    const DevRobot* __restrict__ rb = a.rb;
-    const int n = a.n;
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v);
+__device__ __forceinline__ uint64_t cost_key(float c, uint32_t m);
+
+// Collision test of one lane whose joint values are q[i * q_stride + s];
+// inactive lanes count as done so the wave can leave early.  Returns the
+// collision flag of an active lane.
+__device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, int n, float* lds, int lane,
+                                             bool active, const float* __restrict__ q, int64_t q_stride,
+                                             int64_t s, const float* __restrict__ os, int n_osph,
+                                             const float* __restrict__ ob, int n_obox, uint32_t& n_coarse,
+                                             uint32_t& n_fine) {
     Frame T = identity_frame();
     lds_store_frame(lds, 0, lane, T);
     for (int i = 0; i < n; ++i) {
-        const float th = live ? a.q[(int64_t)i * a.q_stride + s] : 0.f;
+        const float th = active ? q[(int64_t)i * q_stride + s] : 0.f;
         chain_step(rb, i, th, T);
         lds_store_frame(lds, i + 1, lane, T);
     }
-    bool hit = !live;  // padding lanes count as done
-    uint32_t n_coarse = 0, n_fine = 0;
-    const float* __restrict__ os = a.osph;
-    const float* __restrict__ ob = a.obox;
+    bool hit = !active;
     // environment
     for (int l = 0; l <= n && !wave_all(hit); ++l) {
         const float Rc = rb->coarse[l][3];
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
         const Frame F = lds_load_frame(lds, l, lane);
         const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
         const int f0 = rb->link_first[l], fc = rb->link_count[l];
-        for (int o = 0; o < a.n_osph; ++o) {
+        for (int o = 0; o < n_osph; ++o) {
             const V3 co = mk(os[4 * o], os[4 * o + 1], os[4 * o + 2]);
             const float ro = os[4 * o + 3];
             const V3 d = cc - co;
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
                 if (wave_all(hit)) break;
             }
         }
-        for (int o = 0; o < a.n_obox && !wave_all(hit); ++o) {
+        for (int o = 0; o < n_obox && !wave_all(hit); ++o) {
             const float* b = ob + 8 * o;
             const bool ch = !hit && box_d2(cc, b) < Rc * Rc;
             n_coarse += hit ? 0u : 1u;
@@ -171,12 +172,116 @@ __global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
             }
         }
     }
+    return hit;
+}
+
+__global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x;
+    const int64_t s = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = s < a.S;
+    uint32_t n_coarse = 0, n_fine = 0;
+    const bool hit = collide_lane(a.rb, a.n, lds, lane, live, a.q, a.q_stride, s, a.osph, a.n_osph, a.obox,
+                                  a.n_obox, n_coarse, n_fine);
     if (live) a.flag[s] = hit ? 1 : 0;
     if (a.counters) {
         Counters c;
         c.coll_coarse = live ? n_coarse : 0u;
         c.coll_fine = live ? n_fine : 0u;
         flush_counters(c, a.counters, true);
+    }
+}
+
+// Serving: collision test of a chunk's blocks (one wave per block entry).
+__global__ __launch_bounds__(64) void k_serve_check(ServeCheckArgs a) {
+    extern __shared__ float lds[];
+    const int e = blockIdx.x;
+    const int lane = threadIdx.x;
+    const ServeBlock blk = a.blocks[e];
+    const int64_t s = (int64_t)blk.block * 64 + lane;
+    const uint8_t st = a.st.sstate[s];
+    const bool want = (st & SLOT_LIVE) && !(st & SLOT_RETIRED) && !(st & SLOT_CHECKED) &&
+                      (a.all_lanes[e] || (st & SLOT_POL_FROZEN));
+    uint32_t n_coarse = 0, n_fine = 0;
+    const bool hit = collide_lane(a.rb, a.n, lds, lane, want, a.st.q, a.st.C, s, a.osph, a.n_osph, a.obox,
+                                  a.n_obox, n_coarse, n_fine);
+    if (want) a.st.sstate[s] = (uint8_t)(st | SLOT_CHECKED | (hit ? SLOT_COLLIDES : 0));
+}
+
+// Serving: per-target decision, one wave per listed target.
+__global__ __launch_bounds__(64) void k_serve_reduce(ServeReduceArgs a) {
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t f = a.first_slot[i];
+    const int32_t M = a.n_seeds[i];
+    uint64_t best_ok = ~0ull, best_any = ~0ull;
+    for (int32_t m = lane; m < M; m += 64) {
+        const int64_t s = f + m;
+        const uint8_t st = a.st.sstate[s];
+        if (!(st & SLOT_CHECKED)) continue;
+        const bool coll = (st & SLOT_COLLIDES) != 0;
+        const uint64_t key = cost_key(a.st.cost[s], (uint32_t)m);
+        if (!coll && a.st.err_p[s] <= a.succ_pos && a.st.err_o[s] <= a.succ_ori && key < best_ok) best_ok = key;
+        const uint64_t kf = ((uint64_t)coll << 63) | key;
+        if (kf < best_any) best_any = kf;
+    }
+    best_ok = wave_min_u64(best_ok);
+    best_any = wave_min_u64(best_any);
+    int32_t status = 0;
+    uint64_t pick = ~0ull;
+    if (best_ok != ~0ull) {
+        status = 1;
+        pick = best_ok;
+    } else if (a.final_[i]) {
+        status = 2;
+        pick = best_any;
+    }
+    float* row = a.res + (int64_t)i * (a.n + 3);
+    if (status != 0 && pick != ~0ull) {
+        const int64_t s = f + (int64_t)(uint32_t)pick;
+        if (lane < a.n) row[lane] = a.st.q[(int64_t)lane * a.st.C + s];
+        if (lane == 0) {
+            row[a.n] = a.st.err_p[s];
+            row[a.n + 1] = a.st.err_o[s];
+            row[a.n + 2] = (a.st.sstate[s] & SLOT_COLLIDES) ? 1.f : 0.f;
+        }
+    } else if (status != 0) {
+        if (lane < a.n) row[lane] = 0.f;
+        if (lane == 0) {
+            row[a.n] = __builtin_inff();
+            row[a.n + 1] = __builtin_inff();
+            row[a.n + 2] = 255.f;
+        }
+    }
+    if (lane == 0) a.status[i] = status;
+    if (status != 0)
+        for (int32_t m = lane; m < M; m += 64) a.st.sstate[f + m] |= SLOT_RETIRED;
+}
+
+// Serving: slot and target-table initialisation of admitted requests (one
+// workgroup each).
+__global__ __launch_bounds__(256) void k_serve_admit(const ServeAdmit* __restrict__ adm,
+                                                     const float* __restrict__ up_pose, float* __restrict__ tgt_pose,
+                                                     uint32_t* __restrict__ tgt_key, ServeState st) {
+    const ServeAdmit r = adm[blockIdx.x];
+    const int32_t live = r.n_targets * r.M;
+    for (int32_t i = threadIdx.x; i < r.padded; i += blockDim.x) {
+        const int64_t s = r.base + i;
+        if (i < live) {
+            st.sstate[s] = SLOT_LIVE;
+            st.slot_target[s] = r.tbl0 + i / r.M;
+            st.slot_m[s] = (uint32_t)(i % r.M);
+        } else {
+            st.sstate[s] = 0;
+            st.slot_target[s] = 0;
+            st.slot_m[s] = 0;
+        }
+    }
+    for (int32_t k = threadIdx.x; k < r.n_targets; k += blockDim.x) {
+        const float* src = up_pose + (int64_t)(r.up0 + k) * 7;
+#pragma unroll
+        for (int d = 0; d < 7; ++d) tgt_pose[(int64_t)d * st.Tc + r.tbl0 + k] = src[d];
+        tgt_key[r.tbl0 + k] = r.key0 + (uint32_t)k;
     }
 }
 
@@ -367,6 +472,36 @@ hipError_t launch_collide(const CollideArgs& a, hipStream_t st) {
     if (a.S <= 0) return hipSuccess;
     const size_t lds = (size_t)(a.n + 1) * 12 * 64 * sizeof(float);
     hipLaunchKernelGGL(k_collide, dim3(blocks_for(a.S, 64)), dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int NM>
+hipError_t launch_serve_chunk_nm(const ServeChunkArgs& a, hipStream_t st);
+
+hipError_t launch_serve_chunk(const ServeChunkArgs& a, hipStream_t st) {
+    if (a.nb <= 0) return hipSuccess;
+#define L_CHUNK(NMV) return launch_serve_chunk_nm<NMV>(a, st)
+    HJCD_DISPATCH_NM(a.n, L_CHUNK);
+#undef L_CHUNK
+}
+
+hipError_t launch_serve_check(const ServeCheckArgs& a, hipStream_t st) {
+    if (a.nb <= 0) return hipSuccess;
+    const size_t lds = (size_t)(a.n + 1) * 12 * 64 * sizeof(float);
+    hipLaunchKernelGGL(k_serve_check, dim3(a.nb), dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_reduce(const ServeReduceArgs& a, hipStream_t st) {
+    if (a.nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_serve_reduce, dim3(a.nt), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_admit(const ServeAdmit* adm, int32_t n_adm, const float* up_pose, float* tgt_pose,
+                              uint32_t* tgt_key, ServeState sst, hipStream_t st) {
+    if (n_adm <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_serve_admit, dim3(n_adm), dim3(256), 0, st, adm, up_pose, tgt_pose, tgt_key, sst);
     return hipGetLastError();
 }
 

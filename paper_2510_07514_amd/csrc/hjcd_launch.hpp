@@ -120,6 +120,105 @@ hipError_t launch_gather(int n, int32_t T, const int64_t* offsets, const int64_t
                          const int32_t* tperm, int64_t S, int64_t in_stride, const float* q_in,
                          float* q_out, hipStream_t st);
 
+// ---- serving -----------------------------------------------------------------
+// Resident seed slots of the serving loop.  Slots come in blocks of 64 (one
+// wave); every block belongs to one request, so all its lanes share the stage
+// and the iteration range of a chunk.
+enum SlotBits : uint8_t {
+    SLOT_LIVE = 1,       // slot holds a seed
+    SLOT_CD_FROZEN = 2,  // PO-CCD exit test passed
+    SLOT_POL_FROZEN = 4, // PJ-IK exit test passed
+    SLOT_CHECKED = 8,    // collision tested
+    SLOT_COLLIDES = 16,  // collision test result
+    SLOT_RETIRED = 32    // its target is finished: no more work
+};
+enum ServeStage { SERVE_CD = 0, SERVE_POLISH = 1 };
+
+struct ServeBlock {
+    int32_t block;  // slots [64 block, 64 block + 64)
+    int32_t stage;  // ServeStage
+    int32_t k0, k1; // iteration range of this chunk
+};
+
+struct ServeState {
+    float* q;                  // [n][C]
+    uint8_t* sstate;           // [C]
+    int32_t* slot_target;      // [C] target table index
+    uint32_t* slot_m;          // [C] seed index within the target
+    float* err_p;              // [C]
+    float* err_o;              // [C]
+    float* cost;               // [C]
+    int64_t C;
+    const float* tgt_pose;     // [7][Tc]
+    const uint32_t* tgt_key;   // [Tc]
+    int32_t Tc;
+};
+
+struct ServeChunkArgs {
+    const DevRobot* rb;
+    int32_t n;
+    ServeState st;
+    const ServeBlock* blocks;  // [nb]
+    int32_t nb;
+    KernelParams kp;
+    unsigned long long* counters;
+};
+
+hipError_t launch_serve_chunk(const ServeChunkArgs& a, hipStream_t stream);
+
+// Collision test of the blocks' slots that are live, not retired, not yet
+// tested and (all_lanes or PJ-IK-frozen).
+struct ServeCheckArgs {
+    const DevRobot* rb;
+    int32_t n;
+    ServeState st;
+    const ServeBlock* blocks;
+    int32_t nb;
+    const int32_t* all_lanes;  // [nb] 1: test every live lane of the block (end of PJ-IK)
+    const float* osph;
+    int32_t n_osph;
+    const float* obox;
+    int32_t n_obox;
+};
+
+hipError_t launch_serve_check(const ServeCheckArgs& a, hipStream_t stream);
+
+// Per-target decision after a chunk: a target with a tested collision-free
+// seed within (succ_pos, succ_ori) is solved (best such seed by (cost,
+// index)); a target marked final takes its best seed by (flag, cost, index).
+// Finished targets retire their slots.
+struct ServeReduceArgs {
+    ServeState st;
+    int32_t n;
+    const int32_t* targets;    // [nt] target table indices
+    const int64_t* first_slot; // [nt]
+    const int32_t* n_seeds;    // [nt]
+    const int32_t* final_;     // [nt]
+    int32_t nt;
+    float succ_pos, succ_ori;
+    int32_t* status;           // [nt] out: 0 running, 1 solved, 2 finished unsolved
+    float* res;                // [nt][n + 3] out: q, err_p, err_o, flag
+};
+
+hipError_t launch_serve_reduce(const ServeReduceArgs& a, hipStream_t stream);
+
+// Slot and target-table initialisation for admitted requests: slot base + i
+// (i < n_targets * M) gets target tbl0 + i / M, seed index i % M; padding
+// lanes up to `padded` are dead.  Target tbl0 + k takes pose row up0 + k of
+// the upload (AoS [7] floats) and Philox key key0 + k.
+struct ServeAdmit {
+    int64_t base;
+    int32_t n_targets;
+    int32_t M;
+    int32_t padded;  // slots allocated (multiple of 64)
+    int32_t tbl0;    // first target table index (targets of a request are consecutive)
+    int32_t up0;     // first pose row in the upload
+    uint32_t key0;   // Philox key of the request's first target
+};
+
+hipError_t launch_serve_admit(const ServeAdmit* adm, int32_t n_adm, const float* up_pose, float* tgt_pose,
+                              uint32_t* tgt_key, ServeState st, hipStream_t stream);
+
 hipError_t launch_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
                          int64_t count, uint32_t* out, hipStream_t st);
 

@@ -12,11 +12,24 @@
 
 namespace hjcd {
 
+// Occupancy target of the per-seed kernels.  For chains of up to 8 joints
+// three waves per SIMD (at most 168 VGPRs, a few spills) beat the two waves
+// the unconstrained allocation (about 210 VGPRs) allows; larger buckets keep
+// the compiler's choice.  -DHJCD_WAVES_PER_EU=w overrides.
+#if !defined(HJCD_WAVES_PER_EU) && HJCD_NM == 8
+#define HJCD_WAVES_PER_EU 3
+#endif
+#ifdef HJCD_WAVES_PER_EU
+#define HJCD_SOLVE_ATTR __attribute__((amdgpu_waves_per_eu(HJCD_WAVES_PER_EU)))
+#else
+#define HJCD_SOLVE_ATTR
+#endif
+
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
 template <int NM>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
+__global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_solve(SolveArgs a) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
     const int n = a.n;
@@ -43,9 +56,16 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
     }
     Counters cnt;
     Err e{};
-    if (a.do_cd) po_ccd<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, cnt, a.traj, a.S, sl.s, e);
-    if (a.do_polish) pj_ik<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, cnt, a.do_cd ? nullptr : a.traj,
-                               a.S, sl.s, e);
+    if (a.do_cd) {
+        bool frozen = !live;
+        po_ccd<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s, 0, a.kp.cd_sweeps,
+                   e);
+    }
+    if (a.do_polish) {
+        bool frozen = !live;
+        pj_ik<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.do_cd ? nullptr : a.traj, a.S, sl.s,
+                  0, a.kp.polish_iters, e);
+    }
     if (!a.do_cd && !a.do_polish && a.targets) {
         Frame ee;
         V3 Pd[1], Zd[1];
@@ -62,6 +82,71 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs a) {
         if (a.cost) a.cost[sl.s] = cost_of(e);
     }
     flush_counters(cnt, a.counters, a.counters != nullptr);
+}
+
+// ----------------------------------------------------------------------------
+// Serving chunk: wave w of the workgroup advances block entry 4 blockIdx + w
+// by iterations [k0, k1) of its stage; slot state persists in HBM.
+// ----------------------------------------------------------------------------
+template <int NM>
+__global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_serve_chunk(ServeChunkArgs a) {
+    const int e = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (e >= a.nb) return;  // whole wave leaves together
+    const ServeBlock blk = a.blocks[e];
+    const int lane = threadIdx.x & 63;
+    const int64_t s = (int64_t)blk.block * 64 + lane;
+    const int n = a.n;
+    uint8_t st = a.st.sstate[s];
+    const bool live = (st & SLOT_LIVE) && !(st & SLOT_RETIRED);
+    const int32_t t = live ? a.st.slot_target[s] : 0;
+    const uint32_t m = live ? a.st.slot_m[s] : 0u;
+    const uint32_t tkey = live ? a.st.tgt_key[t] : 0u;
+    Target tg = load_target(a.st.tgt_pose, a.st.Tc, t);
+    float th[NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) th[j] = 0.f;
+    if (blk.stage == SERVE_CD && blk.k0 == 0) {
+        uniform_seed<NM>(a.rb, n, th, a.kp.seed, m, tkey);
+    } else if (live) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+            if (j < n) th[j] = a.st.q[(int64_t)j * a.st.C + s];
+    }
+    Counters cnt;
+    Err er{};
+    if (blk.stage == SERVE_CD) {
+        bool frozen = !live || (st & SLOT_CD_FROZEN);
+        po_ccd<NM>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er);
+        if (frozen) st |= SLOT_CD_FROZEN;
+    } else {
+        bool frozen = !live || (st & SLOT_POL_FROZEN);
+        pj_ik<NM>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er);
+        // the exit test of iteration k1 (or the one after the last iteration)
+        // on the state this chunk leaves: a seed converged by the chunk's last
+        // step is eligible for the collision check at this chunk's end
+        if (live && er.ep2 < a.kp.eps_pol2 && er.phi < a.kp.ups_pol) frozen = true;
+        if (frozen) st |= SLOT_POL_FROZEN;
+    }
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+            if (j < n) a.st.q[(int64_t)j * a.st.C + s] = th[j];
+        a.st.err_p[s] = sqrtf(er.ep2);
+        a.st.err_o[s] = er.phi;
+        a.st.cost[s] = cost_of(er);
+        a.st.sstate[s] = st;
+    }
+    flush_counters(cnt, a.counters, a.counters != nullptr);
+}
+
+template <int NM>
+hipError_t launch_serve_chunk_nm(const ServeChunkArgs& a, hipStream_t st);
+
+template <>
+hipError_t launch_serve_chunk_nm<HJCD_NM>(const ServeChunkArgs& a, hipStream_t st) {
+    if (a.nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_serve_chunk<HJCD_NM>, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 template <int NM>

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhjcd.so")
+# HJCD_LIBRARY selects another build of the same ABI (e.g. a tuning variant).
+LIB_PATH = os.environ.get("HJCD_LIBRARY", os.path.join(HERE, "libhjcd.so"))
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_07514_amd.build`")
@@ -34,7 +35,9 @@ SYMBOLS = ("hjcd_ctx_create", "hjcd_ctx_destroy", "hjcd_last_error", "hjcd_param
            "hjcd_version", "hjcd_load_robot", "hjcd_robot_destroy", "hjcd_robot_dof",
            "hjcd_load_scene", "hjcd_scene_destroy", "hjcd_fk", "hjcd_init_seeds", "hjcd_cd",
            "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve",
-           "hjcd_get_stats", "hjcd_philox")
+           "hjcd_get_stats", "hjcd_server_create", "hjcd_server_start", "hjcd_server_submit",
+           "hjcd_server_poll", "hjcd_server_result", "hjcd_server_wait", "hjcd_server_get_stats",
+           "hjcd_server_destroy", "hjcd_philox")
 
 
 class HJCDError(RuntimeError):
@@ -78,6 +81,36 @@ class hjcd_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+HJCD_SERVE_BATCHED = 0
+HJCD_SERVE_PLAIN = 1
+
+
+class hjcd_server_config(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("max_slots", C.c_int64), ("hbm_budget", C.c_size_t),
+                ("max_targets", C.c_int32), ("chunk_iters", C.c_int32), ("max_queue", C.c_int32)]
+
+
+class hjcd_request_info(C.Structure):
+    _fields_ = [("request_id", C.c_int64), ("tag", C.c_uint64), ("n_targets", C.c_int32),
+                ("n_solved", C.c_int32), ("arrival_s", C.c_double), ("admitted_s", C.c_double),
+                ("done_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class hjcd_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("chunks", C.c_int64), ("targets_solved", C.c_int64), ("targets_done", C.c_int64),
+                ("max_slots", C.c_int64), ("resident_slots_peak", C.c_int64),
+                ("mean_resident_slots", C.c_double), ("p50_latency_ms", C.c_double),
+                ("p99_latency_ms", C.c_double), ("first_arrival_s", C.c_double),
+                ("last_done_s", C.c_double), ("solves_per_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp = C.c_void_p
 _i32, _i64, _u64 = C.c_int32, C.c_int64, C.c_uint64
 _lib.hjcd_ctx_create.argtypes = [C.c_int, C.POINTER(_vp)]
@@ -103,8 +136,18 @@ _lib.hjcd_solve.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                             C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hjcd_get_stats.argtypes = [_vp, C.POINTER(hjcd_stats)]
 _lib.hjcd_philox.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+_lib.hjcd_server_create.argtypes = [_vp, _vp, _vp, C.POINTER(hjcd_params), C.POINTER(hjcd_server_config),
+                                    C.POINTER(_vp)]
+_lib.hjcd_server_start.argtypes = [_vp]
+_lib.hjcd_server_submit.argtypes = [_vp, _i32, _vp, _i32, _u64, C.c_double, C.POINTER(_i64)]
+_lib.hjcd_server_poll.argtypes = [_vp, _i32, C.POINTER(hjcd_request_info), C.POINTER(_i32)]
+_lib.hjcd_server_result.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp]
+_lib.hjcd_server_wait.argtypes = [_vp, C.c_double]
+_lib.hjcd_server_get_stats.argtypes = [_vp, C.POINTER(hjcd_server_stats)]
+_lib.hjcd_server_destroy.argtypes = [_vp]
+_lib.hjcd_server_destroy.restype = None
 for _name in SYMBOLS:
-    if _name not in ("hjcd_ctx_destroy", "hjcd_robot_destroy", "hjcd_scene_destroy",
+    if _name not in ("hjcd_ctx_destroy", "hjcd_robot_destroy", "hjcd_scene_destroy", "hjcd_server_destroy",
                      "hjcd_last_error", "hjcd_version", "hjcd_params_default"):
         getattr(_lib, _name).restype = C.c_int32
 
@@ -346,3 +389,77 @@ def hjcd_philox(ctx, ctr, key, count, out, stream=None):
     c, cp = _host(ctr, np.uint32)
     k, kp = _host(key, np.uint32)
     _check(_lib.hjcd_philox(ctx.handle, cp, kp, int(count), _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+
+class Server:
+    def __init__(self, ctx, robot, scene, handle, dof):
+        # keep the context, robot and scene alive as long as the server
+        self.ctx, self.robot, self.scene, self.handle, self.dof = ctx, robot, scene, handle, dof
+
+    def close(self):
+        if self.handle:
+            _lib.hjcd_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hjcd_server_create(ctx, robot, scene, params, mode=HJCD_SERVE_BATCHED, max_slots=0, hbm_budget=0,
+                       max_targets=0, chunk_iters=4, max_queue=0) -> Server:
+    cfg = hjcd_server_config(mode, max_slots, hbm_budget, max_targets, chunk_iters, max_queue)
+    h = _vp()
+    _check(_lib.hjcd_server_create(ctx.handle, robot.handle, scene.handle if scene else None, C.byref(params),
+                                   C.byref(cfg), C.byref(h)))
+    return Server(ctx, robot, scene, h.value, robot.dof)
+
+
+def hjcd_server_start(srv: Server):
+    _check(_lib.hjcd_server_start(srv.handle))
+
+
+def hjcd_server_submit(srv: Server, targets, seeds_per_target: int, tag: int, arrival_s: float) -> int:
+    """targets: host array [n_targets][7] (px py pz qw qx qy qz)."""
+    tg, p = _host(np.asarray(targets, np.float32).reshape(-1, 7), np.float32)
+    rid = _i64()
+    _check(_lib.hjcd_server_submit(srv.handle, tg.shape[0], p, int(seeds_per_target), int(tag) & (2**64 - 1),
+                                   float(arrival_s), C.byref(rid)))
+    return rid.value
+
+
+def hjcd_server_poll(srv: Server, max_n: int = 1024) -> list:
+    buf = (hjcd_request_info * max(1, max_n))()
+    n = _i32()
+    _check(_lib.hjcd_server_poll(srv.handle, max_n, buf, C.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def hjcd_server_result(srv: Server, request_id: int, n_targets: int) -> dict:
+    q = np.zeros((n_targets, srv.dof), np.float32)
+    ep = np.zeros(n_targets, np.float32)
+    eo = np.zeros(n_targets, np.float32)
+    fl = np.zeros(n_targets, np.uint8)
+    _check(_lib.hjcd_server_result(srv.handle, int(request_id), q.ctypes.data, ep.ctypes.data, eo.ctypes.data,
+                                   fl.ctypes.data))
+    return {"q": q, "err_p": ep, "err_o": eo, "flag": fl}
+
+
+def hjcd_server_wait(srv: Server, timeout_s: float):
+    _check(_lib.hjcd_server_wait(srv.handle, float(timeout_s)))
+
+
+def hjcd_server_get_stats(srv: Server) -> dict:
+    st = hjcd_server_stats()
+    _check(_lib.hjcd_server_get_stats(srv.handle, C.byref(st)))
+    return st.as_dict()
+
+
+def hjcd_server_destroy(srv: Server):
+    srv.close()

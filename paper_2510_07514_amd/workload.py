@@ -355,10 +355,13 @@ def config_large(T: int = 100_000, M: int = 256, host_seeds: bool = False) -> Ba
 
 def serving_stream(rate: float, duration: float, seed: int = 4):
     """Poisson request stream for the serving workload: arrival times (s),
-    targets per request U{1..16} (Panda-like, FK of uniform configs), and a
-    per-request seed budget log-uniform in [32, 1024] seeds per target."""
+    targets per request U{1..16} (Panda-like, FK of uniform configs), a
+    per-request seed budget log-uniform in [32, 1024] seeds per target, and
+    the robot (60 link spheres) and 32-sphere scene of the batched workload."""
+    rng2 = np.random.default_rng(2)
+    robot = _panda60(rng2)
+    scene = random_scene(rng2, 32, 0, np.array([-0.6, -0.6, 0.0]), np.array([0.6, 0.6, 1.2]))
     rng = np.random.default_rng(seed)
-    robot = _panda60(np.random.default_rng(2))
     gaps = rng.exponential(1.0 / rate, size=int(rate * duration * 1.3) + 16)
     t = np.cumsum(gaps)
     t = t[t < duration]
@@ -366,8 +369,8 @@ def serving_stream(rate: float, duration: float, seed: int = 4):
     n_tgt = rng.integers(1, 17, size=n_req)
     budget = log_uniform_int(rng, 32, 1024, n_req)
     q_star = [uniform_configs(rng, robot, int(k)) for k in n_tgt]
-    return dict(robot=robot, arrival=t, n_targets=n_tgt, seeds_per_target=budget,
-                q_star=q_star)
+    return dict(robot=robot, scene=scene, arrival=t, n_targets=n_tgt, seeds_per_target=budget,
+                q_star=q_star, params=default_params(top_k=1, rng_seed=4))
 
 
 CONFIGS = {
