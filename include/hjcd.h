@@ -46,6 +46,7 @@ extern "C" {
 #endif
 
 #define HJCD_MAX_DOF 32
+#define HJCD_MAX_ANGLE 1000.0  /* |q_min|, |q_max|, |offset| bound (rad) */
 #define HJCD_MAX_SPHERES 1024
 #define HJCD_MAX_OBSTACLES 65536
 #define HJCD_MAX_TOPK 64

@@ -320,6 +320,10 @@ hjcd_status hjcd_load_robot(hjcd_ctx c, const hjcd_robot_desc* d, hjcd_robot* ou
         for (double x : v)
             if (!std::isfinite(x)) return fail(HJCD_E_INVALID, "joint %d has a non-finite parameter", i);
         if (!(d->q_min[i] <= d->q_max[i])) return fail(HJCD_E_INVALID, "joint %d: q_min > q_max", i);
+        if (std::fabs(d->q_min[i]) > HJCD_MAX_ANGLE || std::fabs(d->q_max[i]) > HJCD_MAX_ANGLE ||
+            std::fabs(d->offset[i]) > HJCD_MAX_ANGLE)
+            return fail(HJCD_E_UNSUPPORTED, "joint %d: limits and offset must lie within +-%g rad", i,
+                        (double)HJCD_MAX_ANGLE);
     }
     double tool[16];
     for (int i = 0; i < 16; ++i) tool[i] = d->tool ? d->tool[i] : (i % 5 == 0 ? 1.0 : 0.0);

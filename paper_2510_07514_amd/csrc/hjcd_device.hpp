@@ -62,6 +62,35 @@ __device__ __forceinline__ Frame identity_frame() {
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) { return fminf(fmaxf(x, lo), hi); }
 
+// sin and cos of x for |x| <= 4096 (every angle here: joint values are
+// clipped to limits the library bounds by 1000 rad, steps are below pi).
+// Cody and Waite's reduction (Software Manual for the Elementary Functions,
+// 1980): k = rint(2x/pi), r = x - k pi/2 with pi/2 split into three floats
+// (each product exact inside an FMA), then the Taylor series of sin to r^9
+// and of cos to r^10 on |r| <= pi/4 and the quadrant k mod 4.  Error about
+// 1.5 ulp, 7e-8 absolute.
+__device__ __forceinline__ void sincos_cw(float x, float* sn, float* cs) {
+    const float k = rintf(x * 0.63661975f);
+    float r = fmaf(-k, 1.57079637f, x);
+    r = fmaf(-k, -4.37113883e-08f, r);
+    r = fmaf(-k, -1.71512451e-15f, r);
+    const float r2 = r * r;
+    float ps = fmaf(2.75573192e-06f, r2, -1.98412698e-04f);
+    ps = fmaf(ps, r2, 8.33333333e-03f);
+    ps = fmaf(ps, r2, -1.66666667e-01f);
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(-2.75573192e-07f, r2, 2.48015873e-05f);
+    pc = fmaf(pc, r2, -1.38888889e-03f);
+    pc = fmaf(pc, r2, 4.16666667e-02f);
+    pc = fmaf(pc, r2, -0.5f);
+    const float cr = fmaf(r2, pc, 1.f);
+    const int q = (int)k;
+    const bool swap = (q & 1) != 0;
+    const float a = swap ? cr : sr, b = swap ? sr : cr;
+    *sn = (q & 2) ? -a : a;
+    *cs = ((q + 1) & 2) ? -b : b;
+}
+
 // ----------------------------------------------------------------------------
 // Forward kinematics (eq. fk): joint origins P_i and axes Z_i (STORE), and the
 // end-effector frame.  Column updates of R * Rx(alpha) * Rz(theta):
@@ -79,7 +108,7 @@ __device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n,
         for (int i = 0; i < NM; ++i) {
             if (i < n) {
                 float s, c;
-                sincosf(th[i] + rb->off[i], &s, &c);
+                sincos_cw(th[i] + rb->off[i], &s, &c);
                 const float ca = rb->ca[i], sa = rb->sa[i];
                 T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
                 V3 Yb = axpy(sa, T.Z, ca * T.Y);
@@ -104,7 +133,7 @@ __device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n,
                     Z[i] = T.Z;
                 }
                 float s, c;
-                sincosf(th[i] + rb->off[i], &s, &c);
+                sincos_cw(th[i] + rb->off[i], &s, &c);
                 const float ca = rb->ca[i], sa = rb->sa[i];
                 V3 Xb = axpy(s, T.Y, c * T.X);
                 V3 Yb = axpy(-s, T.X, c * T.Y);
@@ -136,7 +165,7 @@ __device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n,
 __device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int i, float theta,
                                            Frame& T) {
     float s, c;
-    sincosf(theta + rb->off[i], &s, &c);
+    sincos_cw(theta + rb->off[i], &s, &c);
     const float ca = rb->ca[i], sa = rb->sa[i];
     if (rb->conv == 0) {
         T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
@@ -429,16 +458,21 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                 const float dk = fmaxf(kp.delta_min, delta);
                 // half-angle of the unclamped orientation move |delta(k) phi|
                 float shu, chu;
-                sincosf(0.5f * dk * e.phi, &shu, &chu);
+                sincos_cw(0.5f * dk * e.phi, &shu, &chu);
                 // --- per-joint candidates ---------------------------------
-                // scores in |r_p| (m) and phi (rad) units, kept per joint for the
-                // tie-tolerant pick below
-                float sP[NM], dP[NM], sO[NM], dO[NM];
-                float dmin = 3.4e38f, omin = 3.4e38f;
+                // Position candidates are ranked by their squared residual sp;
+                // orientation candidates by phi' = 2 atan2(|v'|, |w'|) through
+                // the pair (v'^2, w'^2), which orders like tan^2(phi'/2).  Only
+                // the best of each needs its score in m / rad (for the
+                // tie-tolerant pick below).
+                float sPq[NM], dP[NM], oV[NM], oW[NM], dO[NM];
+                float spmin = 3.4e38f;
+                float bv = 1.f, bw = 0.f;  // (v'^2, w'^2) of the best orientation candidate (phi' = pi)
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
-                    sP[j] = 3.4e38f;
-                    sO[j] = 3.4e38f;
+                    sPq[j] = 3.4e38f;
+                    oV[j] = 1.f;
+                    oW[j] = 0.f;
                     dP[j] = 0.f;
                     dO[j] = 0.f;
                     if (j < n) {
@@ -468,15 +502,15 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                             sp = fmaf(az, az, dd * dd);
                         } else {
                             float sh, ch;
-                            sincosf(0.5f * dp, &sh, &ch);
+                            sincos_cw(0.5f * dp, &sh, &ch);
                             const float c2 = 1.f - 2.f * sh * sh, s2 = 2.f * sh * ch;
                             const V3 rw = axpy(s2, cross(z, up), c2 * up);
                             const V3 df = vp - rw;
                             sp = fmaf(az, az, dot(df, df));
                         }
-                        sP[j] = sqrtf(sp);
+                        sPq[j] = sp;
                         dP[j] = dp;
-                        dmin = fminf(dmin, sP[j]);
+                        spmin = fminf(spmin, sp);
                         // eq. (ori_update): delta(k) sgn(a_hat . z) phi
                         const float vzq = e.q.x * z.x + e.q.y * z.y + e.q.z * z.z;
                         const float sg = vzq > 0.f ? 1.f : (vzq < 0.f ? -1.f : 0.f);
@@ -486,26 +520,41 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                         float doc = dor;
                         if (clo) {
                             doc = clampf(tj + dor, lo, hi) - tj;
-                            sincosf(0.5f * doc, &sh, &ch);
+                            sincos_cw(0.5f * doc, &sh, &ch);
                         }
                         const Quat qn = qmul_conj_axis(e.q, z, ch, sh);
-                        const float v2 = qn.x * qn.x + qn.y * qn.y + qn.z * qn.z;
-                        sO[j] = 2.f * atan2f(sqrtf(v2), fabsf(qn.w));
+                        oV[j] = qn.x * qn.x + qn.y * qn.y + qn.z * qn.z;
+                        oW[j] = qn.w * qn.w;
                         dO[j] = doc;
-                        omin = fminf(omin, sO[j]);
+                        // tan^2(phi'_j / 2) < tan^2(phi'_best / 2), cross-multiplied
+                        if (oV[j] * bw < bv * oW[j]) {
+                            bv = oV[j];
+                            bw = oW[j];
+                        }
                     }
                 }
-                // greedy picks: the lowest joint within tie_eps of the best score
+                // greedy picks: the lowest joint whose score lies within tie_eps
+                // of the best: sqrt(sp_j) <= sqrt(sp_min) + tie_eps, and
+                // phi'_j <= phi'_min + tie_eps, i.e. tan^2(phi'_j/2) <=
+                // tan^2(h) with h = (phi'_min + tie_eps) / 2 (every candidate
+                // passes when h >= pi/2)
+                const float dlim = sqrtf(spmin) + kp.tie_eps;
+                const float plim = dlim * dlim;
+                const float hlim = 0.5f * (2.f * atan2f(sqrtf(bv), sqrtf(bw)) + kp.tie_eps);
+                const bool oall = hlim >= 1.5707963f;
+                float sT, cT;
+                sincos_cw(oall ? 0.f : hlim, &sT, &cT);
+                const float sT2 = sT * sT, cT2 = cT * cT;
                 int jp = -1, jo = -1;
                 float dpb = 0.f, dob = 0.f;
 #pragma unroll
                 for (int j = 0; j < NM; ++j) {
                     if (j < n) {
-                        if (jp < 0 && sP[j] <= dmin + kp.tie_eps) {
+                        if (jp < 0 && sPq[j] <= plim) {
                             jp = j;
                             dpb = dP[j];
                         }
-                        if (jo < 0 && sO[j] <= omin + kp.tie_eps) {
+                        if (jo < 0 && (oall || oV[j] * cT2 <= oW[j] * sT2)) {
                             jo = j;
                             dob = dO[j];
                         }
@@ -544,8 +593,8 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                     }
                 }
                 float sha, cha, shb, chb;
-                sincosf(0.5f * da, &sha, &cha);
-                sincosf(0.5f * db, &shb, &chb);
+                sincos_cw(0.5f * da, &sha, &cha);
+                sincos_cw(0.5f * db, &shb, &chb);
                 V3 ph = Pb + rot_half(Zb, chb, shb, ee.p - Pb);
                 ph = Pa + rot_half(Za, cha, sha, ph - Pa);
                 Quat qh = qmul_conj_axis(qmul_conj_axis(e.q, Zb, chb, shb), Za, cha, sha);

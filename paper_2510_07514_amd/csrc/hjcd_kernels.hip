@@ -448,13 +448,25 @@ static inline unsigned blocks_for(int64_t count, int per) { return (unsigned)((c
         }                         \
     } while (0)
 
+// The per-seed solve kernels also come as exact 6- and 7-joint instances.
+#define HJCD_DISPATCH_SOLVE(n, CALL) \
+    do {                             \
+        if ((n) == 6) {              \
+            CALL(6);                 \
+        } else if ((n) == 7) {       \
+            CALL(7);                 \
+        } else {                     \
+            HJCD_DISPATCH_NM(n, CALL); \
+        }                            \
+    } while (0)
+
 template <int NM>
 hipError_t launch_solve_nm(const SolveArgs& a, hipStream_t st);
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st) {
     if (a.map.Sv <= 0) return hipSuccess;
 #define L_SOLVE(NMV) return launch_solve_nm<NMV>(a, st)
-    HJCD_DISPATCH_NM(a.n, L_SOLVE);
+    HJCD_DISPATCH_SOLVE(a.n, L_SOLVE);
 #undef L_SOLVE
 }
 
@@ -481,7 +493,7 @@ hipError_t launch_serve_chunk_nm(const ServeChunkArgs& a, hipStream_t st);
 hipError_t launch_serve_chunk(const ServeChunkArgs& a, hipStream_t st) {
     if (a.nb <= 0) return hipSuccess;
 #define L_CHUNK(NMV) return launch_serve_chunk_nm<NMV>(a, st)
-    HJCD_DISPATCH_NM(a.n, L_CHUNK);
+    HJCD_DISPATCH_SOLVE(a.n, L_CHUNK);
 #undef L_CHUNK
 }
 

@@ -12,11 +12,16 @@
 
 namespace hjcd {
 
+// Buckets below 8 are exact joint counts (the host dispatches a 6- or 7-joint
+// chain to them): the joint loops then have no runtime bound and the chain
+// takes exactly n registers per joint array.
+constexpr bool kExactN = HJCD_NM < 8;
+
 // Occupancy target of the per-seed kernels.  For chains of up to 8 joints
 // three waves per SIMD (at most 168 VGPRs, a few spills) beat the two waves
 // the unconstrained allocation (about 210 VGPRs) allows; larger buckets keep
 // the compiler's choice.  -DHJCD_WAVES_PER_EU=w overrides.
-#if !defined(HJCD_WAVES_PER_EU) && HJCD_NM == 8
+#if !defined(HJCD_WAVES_PER_EU) && HJCD_NM <= 8
 #define HJCD_WAVES_PER_EU 3
 #endif
 #ifdef HJCD_WAVES_PER_EU
@@ -32,7 +37,7 @@ template <int NM>
 __global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_solve(SolveArgs a) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
-    const int n = a.n;
+    const int n = kExactN ? HJCD_NM : a.n;
     Slot sl;
     if (live) {
         sl = map_lane(a.map, v);
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_serve_chunk(ServeChunkA
     const ServeBlock blk = a.blocks[e];
     const int lane = threadIdx.x & 63;
     const int64_t s = (int64_t)blk.block * 64 + lane;
-    const int n = a.n;
+    const int n = kExactN ? HJCD_NM : a.n;
     uint8_t st = a.st.sstate[s];
     const bool live = (st & SLOT_LIVE) && !(st & SLOT_RETIRED);
     const int32_t t = live ? a.st.slot_target[s] : 0;
