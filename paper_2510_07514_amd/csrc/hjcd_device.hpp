@@ -714,6 +714,7 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
         bool done = true;  // lane needs no further fallback this iteration
         float c0 = 0.f;
         float e6[6], w6[6];
+        Quat q0{1.f, 0.f, 0.f, 0.f};  // error quaternion at theta (single-coordinate trials)
         if (!frozen) {
             Frame ee;
             fk_chain<NM, true>(rb, n, th, Jp, Z, ee);
@@ -726,6 +727,7 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                 ++cnt.pol_iters;
                 done = false;
                 c0 = cost_of(e);
+                q0 = e.q;
                 const V3 om = omega_of(e);
                 e6[0] = e.rp.x;
                 e6[1] = e.rp.y;
@@ -962,19 +964,43 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                 }
                 step = hbest > 0.f ? clampf(gbest / hbest, -R, R) : 0.f;
             }
+            // Only joint `is` moves, so a trial pose is the current one turned
+            // about that joint's axis (the same end-effector pose a full FK
+            // gives): with u = P_ee - P_is, z x u = Jp[is] and Rodrigues'
+            // formula, P' = P_ee + sin(d) (z x u) + (1 - cos d) z x (z x u),
+            // and q_err' = q_err (x) conj(q_z(d)).
+            V3 zs = Z[0], js = Jp[0];
+            float ts = th[0], los = rb->lo[0], his = rb->hi[0];
+#pragma unroll
+            for (int j = 0; j < NM; ++j) {
+                if (j < n && j == is) {
+                    zs = Z[j];
+                    js = Jp[j];
+                    ts = th[j];
+                    los = rb->lo[j];
+                    his = rb->hi[j];
+                }
+            }
+            const V3 zjs = cross(zs, js);
+            const V3 rp0 = mk(e6[0], e6[1], e6[2]);
             float alpha2 = 1.f;
             for (int i = 0; i <= kp.ls_A; ++i) {
                 if (wave_all(done)) break;
                 if (!done) {
-#pragma unroll
-                    for (int j = 0; j < NM; ++j)
-                        if (j < n) tt[j] = (j == is) ? clampf(fmaf(alpha2, step, th[j]), rb->lo[j], rb->hi[j]) : th[j];
-                    const float c1 = trial_cost<NM>(rb, n, tg, tt);
+                    const float tnew = clampf(fmaf(alpha2, step, ts), los, his);
+                    float sh, ch;
+                    sincos_cw(0.5f * (tnew - ts), &sh, &ch);
+                    const float sd = 2.f * sh * ch, omc = 2.f * sh * sh;
+                    const V3 rp = axpy(-omc, zjs, axpy(-sd, js, rp0));
+                    const Quat qn = qmul_conj_axis(q0, zs, ch, sh);
+                    const float vn = sqrtf(qn.x * qn.x + qn.y * qn.y + qn.z * qn.z);
+                    const float ph = 2.f * atan2f(vn, fabsf(qn.w));
+                    const float c1 = 0.5f * (dot(rp, rp) + ph * ph);
                     ++cnt.pol_trials;
                     if (c1 < c0) {
 #pragma unroll
                         for (int j = 0; j < NM; ++j)
-                            if (j < n) th[j] = tt[j];
+                            if (j < n && j == is) th[j] = tnew;
                         done = true;
                     }
                 }
