@@ -112,6 +112,130 @@ def cpu_baseline(batch, n_targets):
             "solved": solved, "seconds": dt}
 
 
+def measure(H, ctx, torch, batch, steps, warmup):
+    """Time `steps` whole hjcd_solve calls on one single-robot batch with
+    inputs resident in HBM; the k_solve time comes from the library's HIP
+    events on the launch stream."""
+    rob = batch.robots[0]
+    n, T, k = rob.dof, batch.T, batch.params["top_k"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, batch.scene.spheres, batch.scene.boxes)
+    with torch.cuda.stream(stream):
+        # targets = FK(q*) by the library's own FK kernel
+        qs = torch.as_tensor(np.ascontiguousarray(np.asarray(batch.q_star, np.float32).T)).to(dev)
+        pose = torch.zeros(7, T, device=dev)
+        H.hjcd_fk(ctx, rb, qs, pose, None, stream=stream)
+        targets = pose.contiguous()
+        del qs
+        q_out = torch.zeros(T * k, n, device=dev)
+        ep = torch.zeros(T * k, device=dev)
+        eo = torch.zeros(T * k, device=dev)
+        fl = torch.zeros(T * k, dtype=torch.uint8, device=dev)
+        nf = torch.zeros(T, dtype=torch.int32, device=dev)
+        sv = torch.zeros(T, dtype=torch.uint8, device=dev)
+    p = H.params_from_dict(batch.params, collect_stats=True)
+
+    def step():
+        H.hjcd_solve(ctx, [rb], sc, targets, batch.seed_offsets, p, q_out, ep, eo, fl, nf, sv, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    stream.synchronize()
+    torch.cuda.synchronize()
+    kern_ms, step_ms = [], []
+    agg = None
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        step()
+        st = H.hjcd_get_stats(ctx)  # waits for this step's last event on `stream`
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        kern_ms.append(st["ms_solve_kernel"])
+        if agg is None:
+            agg = {kk: 0 for kk in st}
+        for kk, v in st.items():
+            agg[kk] += v
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    n_solved = int(sv.sum().item())
+    ms_per_step = wall * 1e3 / steps
+    per_step = {kk: v / steps for kk, v in agg.items()}
+    flops = algorithmic_flops(n, per_step)
+    kavg = float(np.mean(kern_ms))
+    achieved = flops / (kavg * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": f"k_solve (fused PO-CCD + PJ-IK, {n} joints)", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
+    return {"value": round(n_solved / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 3),
+            "solved_targets": n_solved, "success_rate": round(n_solved / T, 4),
+            "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                           "p99": round(float(np.percentile(step_ms, 99)), 3)},
+            "stage_ms": {kk: round(per_step[kk], 4) for kk in
+                         ("ms_solve_kernel", "ms_collide", "ms_select", "ms_total")},
+            "work_per_step": {kk: int(per_step[kk]) for kk in
+                              ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
+                               "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},
+            "roofline": roof}
+
+
+def uneven(H, ctx, torch, steps, log):
+    """The uneven batch (4,096 targets over 6-, 7- and 12-joint chains, seeds
+    log-uniform in [16, 2048]): eager hjcd_solve vs one autotuned plan (a
+    hipGraph replay of the whole batch)."""
+    from paper_2510_07514_amd import workload as W
+    b = W.config_uneven()
+    rbs = [H.hjcd_load_robot(ctx, r) for r in b.robots]
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    T, k, n_max = b.T, b.params["top_k"], b.n_max
+    targets = torch.zeros(7, T, device="cuda")
+    for ri, rob in enumerate(b.robots):
+        idx = np.nonzero(b.robot_of_target == ri)[0]
+        qs = np.ascontiguousarray(np.asarray([b.q_star[t] for t in idx], np.float32).T)
+        pose = torch.zeros(7, len(idx), device="cuda")
+        H.hjcd_fk(ctx, rbs[ri], torch.as_tensor(qs).cuda(), pose, None)
+        targets[:, torch.as_tensor(idx).cuda()] = pose
+    torch.cuda.synchronize()
+    outs = [torch.zeros(T * k, n_max, device="cuda"), torch.zeros(T * k, device="cuda"),
+            torch.zeros(T * k, device="cuda"), torch.zeros(T * k, dtype=torch.uint8, device="cuda"),
+            torch.zeros(T, dtype=torch.int32, device="cuda"), torch.zeros(T, dtype=torch.uint8, device="cuda")]
+    p = H.params_from_dict(b.params)
+    stream = torch.cuda.Stream()
+
+    def timed(fn):
+        fn()
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        stream.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_eager = timed(lambda: H.hjcd_solve(ctx, rbs, sc, targets, b.seed_offsets, p, *outs,
+                                          robot_of_target=b.robot_of_target, stream=stream))
+    solved_eager = int(outs[5].sum().item())
+    t0 = time.perf_counter()
+    plan = H.hjcd_plan_create(ctx, rbs, sc, targets, b.seed_offsets, p, *outs, robot_of_target=b.robot_of_target,
+                              tune=True, stream=stream)
+    ms_create = (time.perf_counter() - t0) * 1e3
+    ms_plan = timed(lambda: H.hjcd_plan_execute(plan, stream=stream))
+    solved_plan = int(outs[5].sum().item())
+    choices = [H.hjcd_plan_choice(plan, r) for r in range(len(b.robots))]
+    plan.close()
+    row = {"workload": f"uneven_{T}_targets_{int(b.seed_offsets[-1])}_seeds",
+           "robots": [f"{r.name}:{r.dof}dof" for r in b.robots],
+           "eager": {"ms_per_solve": round(ms_eager, 3), "solves_per_s": round(solved_eager / ms_eager * 1e3, 1)},
+           "plan": {"ms_per_solve": round(ms_plan, 3), "solves_per_s": round(solved_plan / ms_plan * 1e3, 1),
+                    "create_ms_incl_autotune": round(ms_create, 1)},
+           "solved_targets": solved_plan,
+           "choices": [{"variant": c["variant"], "block_threads": c["block_threads"], "ms": round(c["ms"], 3),
+                        "seeds": c["seeds"]} for c in choices]}
+    log(f"uneven: {row}")
+    return row
+
+
 def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
     """Poisson request streams served by the continuous-batching server and
     by the plain one-request-per-launch server (same requests, same keys)."""
@@ -171,6 +295,8 @@ def main():
     ap.add_argument("--cpu-targets", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--large", action="store_true", help="also time the 100,000 x 256 random 20-joint workload")
     ap.add_argument("--serve-rates", default="2000,10000,50000")
     ap.add_argument("--serve-duration", type=float, default=0.25, help="seconds of each request stream")
     ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
@@ -201,70 +327,19 @@ def main():
     from paper_2510_07514_amd import workload as W
 
     batch = W.config_batched(T=args.targets, M=args.seeds, host_seeds=False)
+    ctx = H.hjcd_ctx_create(0)
+    m = measure(H, ctx, torch, batch, args.steps, args.warmup)
     rob = batch.robots[0]
     n, T, k = rob.dof, batch.T, batch.params["top_k"]
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream()
-    ctx = H.hjcd_ctx_create(0)
-    rb = H.hjcd_load_robot(ctx, rob)
-    sc = H.hjcd_load_scene(ctx, batch.scene.spheres, batch.scene.boxes)
-    with torch.cuda.stream(stream):
-        # targets = FK(q*) by the library's own FK kernel
-        qs = torch.as_tensor(np.ascontiguousarray(np.asarray(batch.q_star, np.float32).T)).to(dev)
-        pose = torch.zeros(7, T, device=dev)
-        H.hjcd_fk(ctx, rb, qs, pose, None, stream=stream)
-        targets = pose.contiguous()
-        q_out = torch.zeros(T * k, n, device=dev)
-        ep = torch.zeros(T * k, device=dev)
-        eo = torch.zeros(T * k, device=dev)
-        fl = torch.zeros(T * k, dtype=torch.uint8, device=dev)
-        nf = torch.zeros(T, dtype=torch.int32, device=dev)
-        sv = torch.zeros(T, dtype=torch.uint8, device=dev)
-    p = H.params_from_dict(batch.params, collect_stats=True)
-
-    def step():
-        H.hjcd_solve(ctx, [rb], sc, targets, batch.seed_offsets, p, q_out, ep, eo, fl, nf, sv,
-                     stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    stream.synchronize()
-    torch.cuda.synchronize()
-    kern_ms, step_ms, solved = [], [], []
-    agg = None
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        step()
-        st = H.hjcd_get_stats(ctx)  # waits for this step's last event on `stream`
-        step_ms.append((time.perf_counter() - t0) * 1e3)
-        kern_ms.append(st["ms_solve_kernel"])
-        if agg is None:
-            agg = {kk: 0 for kk in st}
-        for kk, v in st.items():
-            agg[kk] += v
-    stream.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    n_solved = int(sv.sum().item())
-    ms_per_step = wall * 1e3 / args.steps
-    value = n_solved / (ms_per_step / 1e3)
     steps = args.steps
-    per_step = {kk: v / steps for kk, v in agg.items()}
-    flops = algorithmic_flops(n, per_step)
-    kavg = float(np.mean(kern_ms))
-    achieved = flops / (kavg * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": "k_solve (fused PO-CCD + PJ-IK)", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": measured_traffic(), "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
     line = {
         "metric": "collision-free IK solves/s at 1mm/1deg",
-        "value": round(value, 1),
+        "value": m["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -274,20 +349,25 @@ def main():
                    "seeds_per_target": args.seeds, "dof": n, "link_spheres": int(rob.sphere_link.shape[0]),
                    "obstacle_spheres": int(batch.scene.spheres.shape[0]), "top_k": k,
                    "cd_sweeps": batch.params["cd_sweeps"], "polish_iters": batch.params["polish_iters"]},
-        "solved_targets": n_solved,
-        "success_rate": round(n_solved / T, 4),
-        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
-                       "p99": round(float(np.percentile(step_ms, 99)), 3)},
-        "stage_ms": {kk: round(per_step[kk], 4) for kk in
-                     ("ms_solve_kernel", "ms_collide", "ms_select", "ms_total")},
-        "work_per_step": {kk: int(per_step[kk]) for kk in
-                          ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
-                           "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},
-        "roofline": roof,
+        "solved_targets": m["solved_targets"],
+        "success_rate": m["success_rate"],
+        "latency_ms": m["latency_ms"],
+        "stage_ms": m["stage_ms"],
+        "work_per_step": m["work_per_step"],
+        "roofline": dict(m["roofline"], traffic=measured_traffic()),
     }
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    if not args.no_uneven:
+        line["uneven"] = uneven(H, ctx, torch, 5, log)
+    if args.large:
+        lb = W.config_large()
+        ml = measure(H, ctx, torch, lb, 3, 1)
+        line["large"] = dict({"workload": f"large_random20_{lb.T}x{int(lb.seed_offsets[1])}", "top_k": lb.params["top_k"],
+                              "cd_sweeps": lb.params["cd_sweeps"], "polish_iters": lb.params["polish_iters"]}, **ml)
+        log(f"large: {line['large']}")
     if not args.no_serve:
-        def log(msg):
-            print(msg, file=sys.stderr, flush=True)
         rates = [int(x) for x in args.serve_rates.split(",") if x]
         line["serving"] = {"workload": "poisson_panda_1-16_targets_32-1024_seeds", "chunk_iters": args.serve_chunk,
                            "max_slots": args.serve_slots, "duration_s": args.serve_duration,

@@ -234,6 +234,40 @@ hjcd_status hjcd_solve(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots,
  * the stream that call used). */
 hjcd_status hjcd_get_stats(hjcd_ctx ctx, hjcd_stats* out);
 
+/* ---- reusable plans (uneven batches) -----------------------------------------
+ * A plan fixes one batch: robots, scene, targets grouped by robot, seed
+ * offsets, params and the device buffers every execution reads and writes
+ * (the arguments of hjcd_solve).  At creation it uploads the batch layout
+ * once, optionally autotunes the per-seed kernel's launch shape per robot
+ * (occupancy variant x workgroup size, timed on these buffers, fastest
+ * kept), and captures the whole solve into one hipGraph: the robots' solve
+ * and collision kernels on concurrent branches, then the selection.
+ * hjcd_plan_execute replays that graph on a stream: one launch for the whole
+ * uneven batch.  The results equal hjcd_solve's on the same inputs.  Plans
+ * do not resample (resample_K must be 0) and collect no statistics.  The
+ * caller keeps the buffers alive and unchanged in size until
+ * hjcd_plan_destroy; their contents may change between executions. */
+typedef struct hjcd_plan_s* hjcd_plan;
+
+typedef struct {
+    int32_t variant;        /* 0: default occupancy, 1: at least two waves per SIMD */
+    int32_t block_threads;  /* workgroup size of the per-seed kernel */
+    float ms;               /* measured time of the chosen shape (0 when not tuned) */
+    int64_t seeds;          /* seeds of this robot in the batch */
+} hjcd_tune_choice;
+
+hjcd_status hjcd_plan_create(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots, hjcd_scene scene,
+                             int32_t T, const int32_t* robot_of_target /* host, or NULL */,
+                             const float* targets, const int64_t* seed_offsets /* host [T+1] */,
+                             const uint32_t* target_keys, const float* seeds, const hjcd_params* params,
+                             float* q_out, float* err_p, float* err_o, uint8_t* flag, int32_t* n_free,
+                             uint8_t* solved, int32_t tune, void* stream, hjcd_plan* out);
+/* Replay the plan's graph on `stream` (asynchronous). */
+hjcd_status hjcd_plan_execute(hjcd_plan plan, void* stream);
+/* Launch shape used for robot index `robot` of the plan. */
+hjcd_status hjcd_plan_choice(hjcd_plan plan, int32_t robot, hjcd_tune_choice* out);
+void hjcd_plan_destroy(hjcd_plan plan);
+
 /* ---- serving ----------------------------------------------------------------
  * A request loop over one robot and scene.  Requests (a few target poses with
  * a seed budget each) are submitted with a scheduled arrival time on the

@@ -30,7 +30,8 @@ COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
 def _units():
     units = [("hjcd_kernels.o", "hjcd_kernels.hip", []),
              ("hjcd_api.o", "hjcd_api.cpp", ["-x", "hip"]),
-             ("hjcd_server.o", "hjcd_server.cpp", ["-x", "hip"])]
+             ("hjcd_server.o", "hjcd_server.cpp", ["-x", "hip"]),
+             ("hjcd_plan.o", "hjcd_plan.cpp", ["-x", "hip"])]
     for nm in NM_BUCKETS:
         units.append((f"hjcd_solve_nm{nm}.o", "hjcd_solve_inst.hip", [f"-DHJCD_NM={nm}"]))
     return units

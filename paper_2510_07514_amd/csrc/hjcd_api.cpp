@@ -150,7 +150,7 @@ KernelParams hjcd::kparams(const hjcd_params& p) {
     return k;
 }
 
-namespace {
+namespace hjcd {
 
 hjcd_status check_offsets(int32_t T, const int64_t* offs) {
     if (T < 0) return fail(HJCD_E_INVALID, "T must be >= 0");
@@ -179,6 +179,36 @@ hjcd_status check_robot(hjcd_ctx c, hjcd_robot r) {
     if (r->ctx != c) return fail(HJCD_E_INVALID, "robot belongs to another context");
     return HJCD_OK;
 }
+
+void group_targets(int32_t n_robots, int32_t T, const int32_t* robot_of_target, const int64_t* offs,
+                   TargetGroups& g) {
+    g.rb_tb.assign(n_robots + 1, 0);
+    g.perm.clear();
+    g.identity = true;
+    if (robot_of_target && n_robots > 1) {
+        std::vector<int32_t> cnt(n_robots, 0);
+        for (int32_t t = 0; t < T; ++t) cnt[robot_of_target[t]]++;
+        for (int i = 0; i < n_robots; ++i) g.rb_tb[i + 1] = g.rb_tb[i] + cnt[i];
+        g.perm.resize(T);
+        std::vector<int32_t> pos(g.rb_tb.begin(), g.rb_tb.end() - 1);
+        for (int32_t t = 0; t < T; ++t) g.perm[pos[robot_of_target[t]]++] = t;
+        for (int32_t b = 0; b < T; ++b)
+            if (g.perm[b] != b) g.identity = false;
+    } else {
+        const int r0 = robot_of_target ? robot_of_target[0] : 0;
+        for (int i = 0; i <= n_robots; ++i) g.rb_tb[i] = (i <= r0) ? 0 : T;
+    }
+    g.voffs.assign(T + 1, 0);
+    if (g.identity) {
+        std::memcpy(g.voffs.data(), offs, sizeof(int64_t) * (T + 1));
+    } else {
+        for (int32_t b = 0; b < T; ++b) g.voffs[b + 1] = g.voffs[b] + (offs[g.perm[b] + 1] - offs[g.perm[b]]);
+    }
+}
+
+}  // namespace hjcd
+
+namespace {
 
 // ---- stats ------------------------------------------------------------------
 enum StatStage { SS_INIT = 0, SS_CD, SS_RESAMPLE, SS_POLISH, SS_COLLIDE, SS_SELECT, SS_SOLVE };
@@ -366,6 +396,10 @@ hjcd_status hjcd_load_robot(hjcd_ctx c, const hjcd_robot_desc* d, hjcd_robot* ou
         h.px[i] = (float)d->a[i];
         h.py[i] = (float)(-d->d[i] * std::sin(d->alpha[i]));
         h.pz[i] = (float)(d->d[i] * std::cos(d->alpha[i]));
+        // twists of 0 and +-pi/2 (to 1e-9 rad) take exact signed permutations;
+        // the terms dropped are below 1e-9 of the link lengths
+        const double ca = std::cos(d->alpha[i]), sa = std::sin(d->alpha[i]);
+        h.akind[i] = (std::fabs(sa) < 1e-9 && ca > 0) ? 1 : (std::fabs(ca) < 1e-9 ? (sa > 0 ? 2 : 3) : 0);
     }
     bool rot = false;
     for (int i = 0; i < 3; ++i)
@@ -749,31 +783,12 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
     hipStream_t st = (hipStream_t)stream;
 
     // plan: permuted target order grouped by robot, CSR over it
-    std::vector<int32_t> perm;
-    std::vector<int32_t> rb_tb(n_robots + 1, 0);
-    bool identity = true;
-    if (robot_of_target && n_robots > 1) {
-        std::vector<int32_t> cnt(n_robots, 0);
-        for (int32_t t = 0; t < T; ++t) cnt[robot_of_target[t]]++;
-        for (int i = 0; i < n_robots; ++i) rb_tb[i + 1] = rb_tb[i] + cnt[i];
-        perm.resize(T);
-        std::vector<int32_t> pos(rb_tb.begin(), rb_tb.end() - 1);
-        for (int32_t t = 0; t < T; ++t) perm[pos[robot_of_target[t]]++] = t;
-        for (int32_t b = 0; b < T; ++b)
-            if (perm[b] != b) identity = false;
-    } else {
-        const int r0 = robot_of_target ? robot_of_target[0] : 0;
-        for (int i = 0; i <= n_robots; ++i) rb_tb[i] = (i <= r0) ? 0 : T;
-        if (robot_of_target)
-            for (int32_t t = 0; t < T; ++t)
-                if (robot_of_target[t] != r0) identity = false;  // cannot happen with one robot
-    }
-    std::vector<int64_t> voffs(T + 1, 0);
-    if (identity) {
-        std::memcpy(voffs.data(), offs, sizeof(int64_t) * (T + 1));
-    } else {
-        for (int32_t b = 0; b < T; ++b) voffs[b + 1] = voffs[b] + (offs[perm[b] + 1] - offs[perm[b]]);
-    }
+    TargetGroups grp;
+    group_targets(n_robots, T, robot_of_target, offs, grp);
+    const std::vector<int32_t>& perm = grp.perm;
+    const std::vector<int32_t>& rb_tb = grp.rb_tb;
+    const std::vector<int64_t>& voffs = grp.voffs;
+    const bool identity = grp.identity;
     const int32_t K = p->resample_K;
     const int32_t Bp = resample ? (p->resample_B / K) * K : 0;
     const int64_t S2 = resample ? (int64_t)T * Bp : S;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/hjcd.h"
 #include "hjcd_launch.hpp"
@@ -29,6 +30,21 @@ struct DevBuf {
 
 hjcd_status check_params(const hjcd_params* p);
 KernelParams kparams(const hjcd_params& p);
+hjcd_status check_offsets(int32_t T, const int64_t* offs);
+hjcd_status check_robot(hjcd_ctx c, hjcd_robot r);
+
+// Targets of a multi-robot batch regrouped so that each robot's targets (and
+// seeds) are contiguous: perm[b] = caller target of grouped position b,
+// robot i owns grouped targets [rb_tb[i], rb_tb[i+1]), voffs = CSR seed
+// offsets in grouped order; identity when no regrouping was needed.
+struct TargetGroups {
+    std::vector<int32_t> perm;
+    std::vector<int32_t> rb_tb;
+    std::vector<int64_t> voffs;
+    bool identity = true;
+};
+void group_targets(int32_t n_robots, int32_t T, const int32_t* robot_of_target, const int64_t* offs,
+                   TargetGroups& g);
 
 }  // namespace hjcd
 

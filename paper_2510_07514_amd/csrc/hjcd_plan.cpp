@@ -1,0 +1,346 @@
+// Reusable plans of libhjcd: one uneven batch captured into a hipGraph, with
+// the per-seed kernel's launch shape autotuned per robot.  See the plans
+// section of include/hjcd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/hjcd.h"
+#include "hjcd_internal.hpp"
+#include "hjcd_launch.hpp"
+
+using namespace hjcd;
+
+struct hjcd_plan_s {
+    hjcd_ctx ctx = nullptr;
+    int32_t n_robots = 0;
+    hjcd_robot robots[HJCD_MAX_ROBOTS] = {};
+    hjcd_scene scene = nullptr;
+    int32_t T = 0;
+    int n_max = 0;
+    int64_t S = 0;
+    TargetGroups grp;
+    hjcd_params params{};
+    KernelParams kp{};
+    // caller buffers
+    const float* targets = nullptr;
+    const uint32_t* tkeys = nullptr;
+    const float* seeds = nullptr;
+    float *q_out = nullptr, *ep_out = nullptr, *eo_out = nullptr;
+    uint8_t* fl_out = nullptr;
+    int32_t* n_free = nullptr;
+    uint8_t* solved = nullptr;
+    // plan-owned device buffers
+    int64_t* d_voffs = nullptr;
+    int64_t* d_coffs = nullptr;
+    int32_t* d_perm = nullptr;
+    float* qw = nullptr;
+    float* ep = nullptr;
+    float* eo = nullptr;
+    float* cost = nullptr;
+    uint8_t* fl = nullptr;
+    hjcd_tune_choice choice[HJCD_MAX_ROBOTS] = {};
+    hipStream_t main = nullptr;
+    hipStream_t side[HJCD_MAX_ROBOTS] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[HJCD_MAX_ROBOTS] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <typename T>
+hjcd_status dalloc(T** p, size_t count) {
+    if (hipMalloc((void**)p, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+        return fail(HJCD_E_NOMEM, "plan device allocation of %zu bytes failed", sizeof(T) * count);
+    return HJCD_OK;
+}
+
+void plan_free(hjcd_plan p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    void* bufs[] = {p->d_voffs, p->d_coffs, p->d_perm, p->qw, p->ep, p->eo, p->cost, p->fl};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    for (int i = 0; i < HJCD_MAX_ROBOTS; ++i) {
+        if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+        if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+    }
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->main) (void)hipStreamDestroy(p->main);
+}
+
+SolveArgs solve_args(hjcd_plan p, int ri) {
+    SolveArgs a{};
+    a.rb = p->robots[ri]->dev;
+    a.n = p->robots[ri]->n;
+    a.n_rows = p->n_max;
+    SeedMap m{};
+    m.voffs = p->d_voffs;
+    m.tperm = p->grp.identity ? nullptr : p->d_perm;
+    m.T = p->T;
+    m.tb = p->grp.rb_tb[ri];
+    m.te = p->grp.rb_tb[ri + 1];
+    m.base = p->grp.voffs[m.tb];
+    m.Sv = p->grp.voffs[m.te] - p->grp.voffs[m.tb];
+    m.tkeys = p->tkeys;
+    a.map = m;
+    a.S = p->S;
+    a.targets = p->targets;
+    const bool gathered = p->seeds && !p->grp.identity;
+    a.q_in = gathered ? p->qw : p->seeds;
+    a.q_in_stride = p->S;
+    a.q_out = p->qw;
+    a.err_p = p->ep;
+    a.err_o = p->eo;
+    a.cost = p->cost;
+    a.traj = nullptr;
+    a.init_mode = p->seeds ? INIT_LOAD : INIT_UNIFORM;
+    a.do_cd = 1;
+    a.do_polish = 1;
+    a.kp = p->kp;
+    a.counters = nullptr;
+    a.variant = p->choice[ri].variant;
+    a.block_threads = p->choice[ri].block_threads;
+    return a;
+}
+
+CollideArgs collide_args(hjcd_plan p, int ri) {
+    const int64_t base = p->grp.voffs[p->grp.rb_tb[ri]];
+    CollideArgs a{};
+    a.rb = p->robots[ri]->dev;
+    a.n = p->robots[ri]->n;
+    a.S = p->grp.voffs[p->grp.rb_tb[ri + 1]] - base;
+    a.q = p->qw + base;
+    a.q_stride = p->S;
+    a.osph = p->scene ? p->scene->sph : nullptr;
+    a.n_osph = p->scene ? p->scene->n_sph : 0;
+    a.obox = p->scene ? p->scene->box : nullptr;
+    a.n_obox = p->scene ? p->scene->n_box : 0;
+    a.flag = p->fl + base;
+    a.counters = nullptr;
+    return a;
+}
+
+// The whole solve on `st`: per robot, solve then collision on a branch of
+// its own; the selection after every branch has joined.
+hjcd_status enqueue(hjcd_plan p, hipStream_t st) {
+    if (p->seeds && !p->grp.identity)
+        HIP_TRY(launch_gather(p->n_max, p->T, p->d_coffs, p->d_voffs, p->d_perm, p->S, p->S, p->seeds, p->qw, st));
+    HIP_TRY(hipEventRecord(p->fork, st));
+    for (int ri = 0; ri < p->n_robots; ++ri) {
+        if (p->choice[ri].seeds == 0) continue;
+        HIP_TRY(hipStreamWaitEvent(p->side[ri], p->fork, 0));
+        HIP_TRY(launch_solve(solve_args(p, ri), p->side[ri]));
+        HIP_TRY(launch_collide(collide_args(p, ri), p->side[ri]));
+        HIP_TRY(hipEventRecord(p->join[ri], p->side[ri]));
+        HIP_TRY(hipStreamWaitEvent(st, p->join[ri], 0));
+    }
+    SelectArgs a{};
+    a.T = p->T;
+    a.offsets = p->d_voffs;
+    a.tperm = p->grp.identity ? nullptr : p->d_perm;
+    a.n = p->n_max;
+    a.n_stride = p->n_max;
+    a.S = p->S;
+    a.q = p->qw;
+    a.cost = p->cost;
+    a.err_p = p->ep;
+    a.err_o = p->eo;
+    a.flag = p->fl;
+    a.k = p->params.top_k;
+    a.succ_pos = p->params.succ_pos;
+    a.succ_ori = p->params.succ_ori;
+    a.q_out = p->q_out;
+    a.ep_out = p->ep_out;
+    a.eo_out = p->eo_out;
+    a.fl_out = p->fl_out;
+    a.n_free = p->n_free;
+    a.solved = p->solved;
+    HIP_TRY(launch_select(a, st));
+    return HJCD_OK;
+}
+
+// Time each candidate launch shape of robot ri's solve kernel on the plan's
+// buffers (one warm-up and two timed launches) and keep the fastest.
+hjcd_status autotune(hjcd_plan p, int ri) {
+    static const int kBlocks[] = {64, 128, 256};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hjcd_tune_choice best = p->choice[ri];
+    best.ms = 3.4e38f;
+    for (int v = 0; v < 2; ++v) {
+        for (int bt : kBlocks) {
+            p->choice[ri].variant = v;
+            p->choice[ri].block_threads = bt;
+            const SolveArgs a = solve_args(p, ri);
+            HIP_TRY(launch_solve(a, p->main));
+            HIP_TRY(hipEventRecord(e0, p->main));
+            for (int r = 0; r < 2; ++r) HIP_TRY(launch_solve(a, p->main));
+            HIP_TRY(hipEventRecord(e1, p->main));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms *= 0.5f;
+            if (ms < best.ms) {
+                best = p->choice[ri];
+                best.ms = ms;
+            }
+        }
+    }
+    p->choice[ri] = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return HJCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
+                             const int32_t* robot_of_target, const float* targets, const int64_t* offs,
+                             const uint32_t* tkeys, const float* seeds, const hjcd_params* params, float* q_out,
+                             float* err_p, float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved,
+                             int32_t tune, void* stream, hjcd_plan* out) {
+    if (!out) return fail(HJCD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hjcd_status s;
+    if (n_robots < 1 || n_robots > HJCD_MAX_ROBOTS || !robots)
+        return fail(HJCD_E_INVALID, "need 1..%d robots", HJCD_MAX_ROBOTS);
+    if ((s = check_params(params)) != HJCD_OK) return s;
+    if (params->resample_K > 0) return fail(HJCD_E_UNSUPPORTED, "plans do not resample (resample_K must be 0)");
+    if ((s = check_offsets(T, offs)) != HJCD_OK) return s;
+    if (T < 1) return fail(HJCD_E_INVALID, "a plan needs T >= 1");
+    if (robot_of_target)
+        for (int32_t t = 0; t < T; ++t)
+            if (robot_of_target[t] < 0 || robot_of_target[t] >= n_robots)
+                return fail(HJCD_E_INVALID, "robot_of_target[%d] = %d out of range", t, robot_of_target[t]);
+    if (!targets || !q_out || !err_p || !err_o || !flag || !n_free || !solved)
+        return fail(HJCD_E_INVALID, "targets and outputs are required");
+    if (!c) return fail(HJCD_E_INVALID, "ctx is NULL");
+    for (int i = 0; i < n_robots; ++i)
+        if ((s = check_robot(c, robots[i])) != HJCD_OK) return s;
+    if (sc && sc->ctx != c) return fail(HJCD_E_INVALID, "scene belongs to another context");
+    HIP_TRY(hipSetDevice(c->device));
+
+    auto* p = new hjcd_plan_s();
+    auto bail = [&](hjcd_status st) {
+        plan_free(p);
+        delete p;
+        return st;
+    };
+    p->ctx = c;
+    p->n_robots = n_robots;
+    for (int i = 0; i < n_robots; ++i) p->robots[i] = robots[i];
+    p->scene = sc;
+    p->T = T;
+    for (int i = 0; i < n_robots; ++i) p->n_max = std::max(p->n_max, robots[i]->n);
+    p->S = offs[T];
+    p->params = *params;
+    p->params.collect_stats = 0;
+    p->kp = kparams(p->params);
+    p->targets = targets;
+    p->tkeys = tkeys;
+    p->seeds = seeds;
+    p->q_out = q_out;
+    p->ep_out = err_p;
+    p->eo_out = err_o;
+    p->fl_out = flag;
+    p->n_free = n_free;
+    p->solved = solved;
+    group_targets(n_robots, T, robot_of_target, offs, p->grp);
+    for (int ri = 0; ri < n_robots; ++ri) {
+        p->choice[ri].variant = 0;
+        p->choice[ri].block_threads = 256;
+        p->choice[ri].ms = 0.f;
+        p->choice[ri].seeds = p->grp.voffs[p->grp.rb_tb[ri + 1]] - p->grp.voffs[p->grp.rb_tb[ri]];
+    }
+    const size_t S1 = (size_t)std::max<int64_t>(p->S, 1);
+    if ((s = dalloc(&p->d_voffs, T + 1)) != HJCD_OK || (s = dalloc(&p->d_coffs, T + 1)) != HJCD_OK ||
+        (s = dalloc(&p->d_perm, T)) != HJCD_OK || (s = dalloc(&p->qw, (size_t)p->n_max * S1)) != HJCD_OK ||
+        (s = dalloc(&p->ep, S1)) != HJCD_OK || (s = dalloc(&p->eo, S1)) != HJCD_OK ||
+        (s = dalloc(&p->cost, S1)) != HJCD_OK || (s = dalloc(&p->fl, S1)) != HJCD_OK)
+        return bail(s);
+    if (hipStreamCreateWithFlags(&p->main, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(HJCD_E_DEVICE, "plan stream / event creation failed"));
+    for (int ri = 0; ri < n_robots; ++ri)
+        if (hipStreamCreateWithFlags(&p->side[ri], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->join[ri], hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HJCD_E_DEVICE, "plan stream / event creation failed"));
+    // the batch layout, uploaded once
+    hipStream_t ust = p->main;
+    if (hipMemcpyAsync(p->d_voffs, p->grp.voffs.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, ust) !=
+            hipSuccess ||
+        hipMemcpyAsync(p->d_coffs, offs, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, ust) != hipSuccess ||
+        (!p->grp.identity &&
+         hipMemcpyAsync(p->d_perm, p->grp.perm.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, ust) !=
+             hipSuccess) ||
+        hipStreamSynchronize(ust) != hipSuccess)
+        return bail(fail(HJCD_E_DEVICE, "plan upload failed"));
+    // the caller's stream (NULL: the default stream) may still be producing
+    // the inputs the autotuner reads
+    {
+        hipEvent_t ready;
+        if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(HJCD_E_DEVICE, "plan event creation failed"));
+        const bool ok = hipEventRecord(ready, (hipStream_t)stream) == hipSuccess &&
+                        hipStreamWaitEvent(p->main, ready, 0) == hipSuccess;
+        (void)hipEventDestroy(ready);
+        if (!ok) return bail(fail(HJCD_E_DEVICE, "plan stream ordering failed"));
+    }
+    if (tune) {
+        if (p->seeds && !p->grp.identity &&
+            launch_gather(p->n_max, T, p->d_coffs, p->d_voffs, p->d_perm, p->S, p->S, p->seeds, p->qw, p->main) !=
+                hipSuccess)
+            return bail(fail(HJCD_E_DEVICE, "seed gather failed"));
+        for (int ri = 0; ri < n_robots; ++ri)
+            if (p->choice[ri].seeds > 0 && (s = autotune(p, ri)) != HJCD_OK) return bail(s);
+    }
+    // capture
+    if (hipStreamBeginCapture(p->main, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(fail(HJCD_E_DEVICE, "graph capture could not start"));
+    s = enqueue(p, p->main);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->main, &g);
+    if (s != HJCD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return bail(s);
+    }
+    if (ec != hipSuccess) return bail(fail(HJCD_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec)));
+    p->graph = g;
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(HJCD_E_DEVICE, "graph instantiation failed"));
+    *out = p;
+    return HJCD_OK;
+}
+
+hjcd_status hjcd_plan_execute(hjcd_plan p, void* stream) {
+    if (!p) return fail(HJCD_E_INVALID, "plan is NULL");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+    return HJCD_OK;
+}
+
+hjcd_status hjcd_plan_choice(hjcd_plan p, int32_t robot, hjcd_tune_choice* out) {
+    if (!p || !out) return fail(HJCD_E_INVALID, "plan and out are required");
+    if (robot < 0 || robot >= p->n_robots) return fail(HJCD_E_INVALID, "robot %d out of range", robot);
+    *out = p->choice[robot];
+    return HJCD_OK;
+}
+
+void hjcd_plan_destroy(hjcd_plan p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    if (p->main) (void)hipStreamSynchronize(p->main);
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    delete p;
+}
+
+}  // extern "C"

@@ -17,24 +17,22 @@ namespace hjcd {
 // takes exactly n registers per joint array.
 constexpr bool kExactN = HJCD_NM < 8;
 
-// Occupancy target of the per-seed kernels.  For chains of up to 8 joints
-// three waves per SIMD (at most 168 VGPRs, a few spills) beat the two waves
-// the unconstrained allocation (about 210 VGPRs) allows; larger buckets keep
-// the compiler's choice.  -DHJCD_WAVES_PER_EU=w overrides.
-#if !defined(HJCD_WAVES_PER_EU) && HJCD_NM <= 8
-#define HJCD_WAVES_PER_EU 3
-#endif
-#ifdef HJCD_WAVES_PER_EU
-#define HJCD_SOLVE_ATTR __attribute__((amdgpu_waves_per_eu(HJCD_WAVES_PER_EU)))
-#else
-#define HJCD_SOLVE_ATTR
-#endif
+// Occupancy variants of the per-seed solve kernel (a launch-shape choice of
+// the autotuner; the arithmetic is the same).  Variant 0: three waves per
+// SIMD for chains of up to 8 joints (at most 168 VGPRs, a few spills, faster
+// than the two waves of the unconstrained allocation), the compiler's choice
+// above.  Variant 1: at least two waves per SIMD (at most 256 VGPRs).
+template <int NM, int V>
+struct SolveOcc {
+    static constexpr int waves = V == 0 ? (NM <= 8 ? 3 : 1) : 2;
+};
 
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
-template <int NM>
-__global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_solve(SolveArgs a) {
+template <int NM, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
+    SolveArgs a) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
     const int n = kExactN ? HJCD_NM : a.n;
@@ -94,7 +92,8 @@ __global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_solve(SolveArgs a) {
 // by iterations [k0, k1) of its stage; slot state persists in HBM.
 // ----------------------------------------------------------------------------
 template <int NM>
-__global__ __launch_bounds__(256) HJCD_SOLVE_ATTR void k_serve_chunk(ServeChunkArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, 0>::waves))) void k_serve_chunk(
+    ServeChunkArgs a) {
     const int e = (int)(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (e >= a.nb) return;  // whole wave leaves together
     const ServeBlock blk = a.blocks[e];
@@ -159,8 +158,12 @@ hipError_t launch_solve_nm(const SolveArgs& a, hipStream_t st);
 
 template <>
 hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
-    const unsigned nb = (unsigned)((a.map.Sv + 255) / 256);
-    hipLaunchKernelGGL(k_solve<HJCD_NM>, dim3(nb), dim3(256), 0, st, a);
+    const int bt = a.block_threads > 0 ? a.block_threads : 256;
+    const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
+    if (a.variant == 1)
+        hipLaunchKernelGGL((k_solve<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_solve<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
     return hipGetLastError();
 }
 

@@ -35,7 +35,8 @@ SYMBOLS = ("hjcd_ctx_create", "hjcd_ctx_destroy", "hjcd_last_error", "hjcd_param
            "hjcd_version", "hjcd_load_robot", "hjcd_robot_destroy", "hjcd_robot_dof",
            "hjcd_load_scene", "hjcd_scene_destroy", "hjcd_fk", "hjcd_init_seeds", "hjcd_cd",
            "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve",
-           "hjcd_get_stats", "hjcd_server_create", "hjcd_server_start", "hjcd_server_submit",
+           "hjcd_get_stats", "hjcd_plan_create", "hjcd_plan_execute", "hjcd_plan_choice", "hjcd_plan_destroy",
+           "hjcd_server_create", "hjcd_server_start", "hjcd_server_submit",
            "hjcd_server_poll", "hjcd_server_result", "hjcd_server_wait", "hjcd_server_get_stats",
            "hjcd_server_destroy", "hjcd_philox")
 
@@ -83,6 +84,13 @@ class hjcd_stats(C.Structure):
 
 HJCD_SERVE_BATCHED = 0
 HJCD_SERVE_PLAIN = 1
+
+
+class hjcd_tune_choice(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("block_threads", C.c_int32), ("ms", C.c_float), ("seeds", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class hjcd_server_config(C.Structure):
@@ -136,6 +144,12 @@ _lib.hjcd_solve.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                             C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hjcd_get_stats.argtypes = [_vp, C.POINTER(hjcd_stats)]
 _lib.hjcd_philox.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
+_lib.hjcd_plan_create.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, C.POINTER(hjcd_params),
+                                  _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, C.POINTER(_vp)]
+_lib.hjcd_plan_execute.argtypes = [_vp, _vp]
+_lib.hjcd_plan_choice.argtypes = [_vp, _i32, C.POINTER(hjcd_tune_choice)]
+_lib.hjcd_plan_destroy.argtypes = [_vp]
+_lib.hjcd_plan_destroy.restype = None
 _lib.hjcd_server_create.argtypes = [_vp, _vp, _vp, C.POINTER(hjcd_params), C.POINTER(hjcd_server_config),
                                     C.POINTER(_vp)]
 _lib.hjcd_server_start.argtypes = [_vp]
@@ -148,6 +162,7 @@ _lib.hjcd_server_destroy.argtypes = [_vp]
 _lib.hjcd_server_destroy.restype = None
 for _name in SYMBOLS:
     if _name not in ("hjcd_ctx_destroy", "hjcd_robot_destroy", "hjcd_scene_destroy", "hjcd_server_destroy",
+                     "hjcd_plan_destroy",
                      "hjcd_last_error", "hjcd_version", "hjcd_params_default"):
         getattr(_lib, _name).restype = C.c_int32
 
@@ -389,6 +404,60 @@ def hjcd_philox(ctx, ctr, key, count, out, stream=None):
     c, cp = _host(ctr, np.uint32)
     k, kp = _host(key, np.uint32)
     _check(_lib.hjcd_philox(ctx.handle, cp, kp, int(count), _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# reusable plans
+# ---------------------------------------------------------------------------
+
+class Plan:
+    def __init__(self, keep, handle, n_robots):
+        # keep the context, robots, scene and buffers alive as long as the plan
+        self.keep, self.handle, self.n_robots = keep, handle, n_robots
+
+    def close(self):
+        if self.handle:
+            _lib.hjcd_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hjcd_plan_create(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, err_o, flag, n_free,
+                     solved, robot_of_target=None, seeds=None, target_keys=None, tune=True, stream=None) -> Plan:
+    """A reusable, graph-captured solve of one batch; see include/hjcd.h."""
+    if isinstance(robots, Robot):
+        robots = [robots]
+    arr = (_vp * len(robots))(*[r.handle for r in robots])
+    offs, op = _host(seed_offsets, np.int64)
+    rot, rotp = None, None
+    if robot_of_target is not None:
+        rot, rotp = _host(robot_of_target, np.int32)
+    h = _vp()
+    _check(_lib.hjcd_plan_create(ctx.handle, len(robots), C.cast(arr, _vp), scene.handle if scene else None,
+                                 int(offs.shape[0] - 1), rotp, _ptr(targets), op, _ptr(target_keys), _ptr(seeds),
+                                 C.byref(params), _ptr(q_out), _ptr(err_p), _ptr(err_o), _ptr(flag), _ptr(n_free),
+                                 _ptr(solved), 1 if tune else 0, _stream(stream), C.byref(h)))
+    keep = (ctx, list(robots), scene, targets, q_out, err_p, err_o, flag, n_free, solved, seeds, target_keys)
+    return Plan(keep, h.value, len(robots))
+
+
+def hjcd_plan_execute(plan: Plan, stream=None):
+    _check(_lib.hjcd_plan_execute(plan.handle, _stream(stream)))
+
+
+def hjcd_plan_choice(plan: Plan, robot: int) -> dict:
+    ch = hjcd_tune_choice()
+    _check(_lib.hjcd_plan_choice(plan.handle, int(robot), C.byref(ch)))
+    return ch.as_dict()
+
+
+def hjcd_plan_destroy(plan: Plan):
+    plan.close()
 
 
 # ---------------------------------------------------------------------------

@@ -454,3 +454,53 @@ def test_full_size_sampled_parity(H, ctx):
             fails.append((int(s), kk, w))
     say(f"  polish sampled {len(cols)} seeds: tie-affected {ties}, fails {fails[:5]}")
     assert not fails
+
+
+def test_large_full_size_sampled(H, ctx):
+    """The large configuration at full size (random 20-joint chain, 100,000
+    targets x 256 seeds, 40 + 40 iterations, 128 spheres + 128 boxes, top-16)
+    in one hjcd_solve; a sample of 8 targets is re-solved by the oracle (all
+    their seeds): solved flags agree on all but one, and every returned
+    configuration reproduces its reported errors and collision flag."""
+    import torch
+    say("case: large full-size solve, sampled oracle targets")
+    b = W.config_large()
+    rob = b.robots[0]
+    n, T, k = rob.dof, b.T, b.params["top_k"]
+    rng = np.random.default_rng(11)
+    tsel = np.sort(rng.choice(T, size=8, replace=False))
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    qs = torch.as_tensor(np.ascontiguousarray(np.asarray(b.q_star, np.float32).T)).cuda()
+    pose = torch.zeros(7, T, device="cuda")
+    H.hjcd_fk(ctx, rb, qs, pose, None)
+    o = dict(q=torch.zeros(T * k, n, device="cuda"), ep=torch.zeros(T * k, device="cuda"),
+             eo=torch.zeros(T * k, device="cuda"), fl=torch.zeros(T * k, dtype=torch.uint8, device="cuda"),
+             nf=torch.zeros(T, dtype=torch.int32, device="cuda"), sv=torch.zeros(T, dtype=torch.uint8, device="cuda"))
+    p = H.params_from_dict(b.params)
+    H.hjcd_solve(ctx, [rb], sc, pose, b.seed_offsets, p, o["q"], o["ep"], o["eo"], o["fl"], o["nf"], o["sv"])
+    _sync()
+    rows = torch.as_tensor(np.concatenate([np.arange(t * k, (t + 1) * k) for t in tsel])).cuda()
+    q = o["q"][rows].cpu().numpy().reshape(8, k, n)
+    ep = o["ep"][rows].cpu().numpy().reshape(8, k)
+    eo = o["eo"][rows].cpu().numpy().reshape(8, k)
+    fl = o["fl"][rows].cpu().numpy().reshape(8, k)
+    sv = o["sv"].cpu().numpy()[tsel]
+    nf = o["nf"].cpu().numpy()[tsel]
+    say(f"  gpu: solved {int(o['sv'].sum().item())}/{T}; sample solved {sv.tolist()} n_free {nf.tolist()}")
+    tg = O.targets_from_qstar(rob, [b.q_star[t] for t in tsel]).astype(np.float64)
+    M = int(b.seed_offsets[1] - b.seed_offsets[0])
+    ref = O.solve(rob, b.scene, tg, np.arange(9, dtype=np.int64) * M, b.params, seeds=None,
+                  target_keys=tsel.astype(np.uint32), nthreads=0)
+    say(f"  oracle: sample solved {ref['solved'].tolist()} n_free {ref['n_free'].tolist()}")
+    assert np.sum(sv == ref["solved"]) >= 7
+    for i in range(8):
+        for r in range(k):
+            if fl[i, r] == 255:
+                continue
+            f = O.fk(rob, q[i, r].astype(np.float64))
+            e = O.residual(tg[i][:3], tg[i][3:], f["p_ee"], f["R_ee"])
+            assert abs(np.linalg.norm(e["rp"]) - ep[i, r]) < 2e-5
+            hit, md = O.collide(rob, b.scene, q[i, r].astype(np.float64))
+            if abs(md) > 1e-5:
+                assert hit == int(fl[i, r]), (i, r, md)
