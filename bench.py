@@ -7,10 +7,13 @@ spheres, 32 obstacle spheres, top-8 (the batched configuration).
 
 Prints one JSON line.  `value` = collision-free solves per second at 1 mm /
 1 deg (targets with a returned collision-free seed within tolerance, per
-second of wall time).  `roofline` prices the fused PO-CCD + PJ-IK kernel's
-algorithmic FP32 flops (per-unit counts x executed units, counted live by
-the kernel) against the MI355X FP32 vector peak; `cpu_baseline` times the
-FP64 oracle on a bounded sample of the same workload on the host cores.
+second of wall time).  `roofline` prices the dominant kernel, PJ-IK
+(k_polish), by its algorithmic FP32 flops (per-unit counts x executed units,
+counted live by the kernel) against the MI355X FP32 vector peak, with the
+PO-CCD kernel's figures beside it; `cpu_baseline` times the FP64 oracle on a
+bounded sample of the same workload on the host cores.  Further sections:
+the uneven multi-robot batch (eager vs graph plan), the serving streams
+(served vs plain) and, with --large, the 100,000 x 256 20-joint workload.
 """
 from __future__ import annotations
 
@@ -56,6 +59,16 @@ def unit_flops(n, modified=True, tool_rot=False):
     )
 
 
+def stage_flops(n, st, modified=True, tool_rot=False):
+    """(PO-CCD kernel, PJ-IK kernel) algorithmic flops of one solve."""
+    u = unit_flops(n, modified, tool_rot)
+    final = fk_flops(n, modified, tool_rot) + RESIDUAL + 1
+    cd = st["cd_iters"] * u["cd_iter"] + st["cd_perturb"] * u["perturb"] + st["seeds"] * (5 * n + final)
+    pol = (st["pol_iters"] * u["pol_iter"] + st["pol_trials"] * u["pol_trial"] + st["pol_dogleg"] * u["pol_dogleg"]
+           + st["pol_single"] * u["pol_single"] + st["pol_perturb"] * u["perturb"] + st["seeds"] * final)
+    return cd, pol
+
+
 def algorithmic_flops(n, st, modified=True, tool_rot=False):
     u = unit_flops(n, modified, tool_rot)
     return (st["cd_iters"] * u["cd_iter"] + st["pol_iters"] * u["pol_iter"]
@@ -64,7 +77,7 @@ def algorithmic_flops(n, st, modified=True, tool_rot=False):
             + (st["cd_perturb"] + st["pol_perturb"]) * u["perturb"] + st["seeds"] * u["seed"])
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_solve_batched_panda_1000x1024_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_polish_batched_panda_1000x1024_traffic.txt")
 KERNEL_SOURCES = ("hjcd_device.hpp", "hjcd_launch.hpp", "hjcd_solve_inst.hip")
 
 
@@ -78,7 +91,7 @@ def kernel_sources_sha():
 
 
 def measured_traffic():
-    """HBM bytes per k_solve launch from the committed FETCH_SIZE / WRITE_SIZE
+    """HBM bytes per k_polish launch from the committed FETCH_SIZE / WRITE_SIZE
     counter runs (scaled by the plain-copy calibration), or None when the
     kernel's sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
@@ -152,7 +165,7 @@ def measure(H, ctx, torch, batch, steps, warmup):
         step()
         st = H.hjcd_get_stats(ctx)  # waits for this step's last event on `stream`
         step_ms.append((time.perf_counter() - t0) * 1e3)
-        kern_ms.append(st["ms_solve_kernel"])
+        kern_ms.append(st["ms_polish"])
         if agg is None:
             agg = {kk: 0 for kk in st}
         for kk, v in st.items():
@@ -163,18 +176,23 @@ def measure(H, ctx, torch, batch, steps, warmup):
     n_solved = int(sv.sum().item())
     ms_per_step = wall * 1e3 / steps
     per_step = {kk: v / steps for kk, v in agg.items()}
-    flops = algorithmic_flops(n, per_step)
+    f_cd, f_pol = stage_flops(n, per_step)
     kavg = float(np.mean(kern_ms))
-    achieved = flops / (kavg * 1e-3) / 1e12
-    roof = {"bound": "alu", "kernel": f"k_solve (fused PO-CCD + PJ-IK, {n} joints)", "achieved": round(achieved, 3),
+    achieved = f_pol / (kavg * 1e-3) / 1e12
+    cd_ms = per_step["ms_cd"]
+    roof = {"bound": "alu", "kernel": f"k_polish (PJ-IK, {n} joints)", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(flops / 1e9, 3)}
+            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(f_pol / 1e9, 3),
+            "cd_kernel": {"kernel": "k_cd (PO-CCD)", "kernel_ms": round(cd_ms, 4),
+                          "algorithmic_gflop_per_launch": round(f_cd / 1e9, 3),
+                          "achieved": round(f_cd / (cd_ms * 1e-3) / 1e12, 3) if cd_ms > 0 else None},
+            "both_stages_achieved": round((f_cd + f_pol) / ((kavg + cd_ms) * 1e-3) / 1e12, 3)}
     return {"value": round(n_solved / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 3),
             "solved_targets": n_solved, "success_rate": round(n_solved / T, 4),
             "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                            "p99": round(float(np.percentile(step_ms, 99)), 3)},
             "stage_ms": {kk: round(per_step[kk], 4) for kk in
-                         ("ms_solve_kernel", "ms_collide", "ms_select", "ms_total")},
+                         ("ms_cd", "ms_resample", "ms_polish", "ms_collide", "ms_select", "ms_total")},
             "work_per_step": {kk: int(per_step[kk]) for kk in
                               ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
                                "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},

@@ -396,10 +396,6 @@ hjcd_status hjcd_load_robot(hjcd_ctx c, const hjcd_robot_desc* d, hjcd_robot* ou
         h.px[i] = (float)d->a[i];
         h.py[i] = (float)(-d->d[i] * std::sin(d->alpha[i]));
         h.pz[i] = (float)(d->d[i] * std::cos(d->alpha[i]));
-        // twists of 0 and +-pi/2 (to 1e-9 rad) take exact signed permutations;
-        // the terms dropped are below 1e-9 of the link lengths
-        const double ca = std::cos(d->alpha[i]), sa = std::sin(d->alpha[i]);
-        h.akind[i] = (std::fabs(sa) < 1e-9 && ca > 0) ? 1 : (std::fabs(ca) < 1e-9 ? (sa > 0 ? 2 : 3) : 0);
     }
     bool rot = false;
     for (int i = 0; i < 3; ++i)
@@ -858,31 +854,40 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
     };
 
     if (!resample) {
-        // fused PO-CCD + PJ-IK per robot
-        for (int ri = 0; ri < n_robots; ++ri) {
+        // PO-CCD per robot, then PJ-IK per robot: two kernels, each compiled
+        // for its stage alone (fewer live registers than one fused kernel)
+        auto stage_args = [&](int ri, bool cd) {
             SolveArgs a{};
             a.rb = robots[ri]->dev;
             a.n = robots[ri]->n;
             a.n_rows = n_max;
             a.map = make_map(ri, d_voffs, -1);
-            if (a.map.Sv == 0) continue;
             a.S = S;
             a.targets = targets;
-            a.q_in = q_src;
-            a.q_in_stride = q_src_stride;
+            a.q_in = cd ? q_src : qw;
+            a.q_in_stride = cd ? q_src_stride : S;
             a.q_out = qw;
             a.err_p = (float*)c->ep.p;
             a.err_o = (float*)c->eo.p;
             a.cost = (float*)c->cost.p;
             a.traj = nullptr;
-            a.init_mode = seeds ? INIT_LOAD : INIT_UNIFORM;
-            a.do_cd = 1;
-            a.do_polish = 1;
+            a.init_mode = cd ? (seeds ? INIT_LOAD : INIT_UNIFORM) : INIT_LOAD;
+            a.do_cd = cd ? 1 : 0;
+            a.do_polish = cd ? 0 : 1;
             a.kp = kp;
             a.counters = ss.counters();
-            HIP_TRY(launch_solve(a, st));
+            return a;
+        };
+        for (int ri = 0; ri < n_robots; ++ri) {
+            const SolveArgs a = stage_args(ri, true);
+            if (a.map.Sv > 0) HIP_TRY(launch_solve(a, st));
         }
-        if ((s = ss.mark(SS_SOLVE)) != HJCD_OK) return s;
+        if ((s = ss.mark(SS_CD)) != HJCD_OK) return s;
+        for (int ri = 0; ri < n_robots; ++ri) {
+            const SolveArgs a = stage_args(ri, false);
+            if (a.map.Sv > 0) HIP_TRY(launch_solve(a, st));
+        }
+        if ((s = ss.mark(SS_POLISH)) != HJCD_OK) return s;
     } else {
         for (int ri = 0; ri < n_robots; ++ri) {
             SolveArgs a{};

@@ -98,77 +98,51 @@ __device__ __forceinline__ void sincos_cw(float x, float* sn, float* cs) {
 //                joint i = frame i
 //   standard DH: joint i = frame i-1; p += a (R Rz(theta)).X + d R.Z;
 //                R <- R Rz(theta) Rx(alpha)
-// A twist alpha of 0 or +-pi/2 (the table's akind 1..3; the common case)
-// turns (Y, Z) by a signed permutation and drops a zero offset term.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ V3 neg(V3 a) { return mk(-a.x, -a.y, -a.z); }
-
-// (Y, Z) <- (sa Z + ca Y, -sa Y + ca Z)
-__device__ __forceinline__ void twist_x(int kind, float ca, float sa, V3& Y, V3& Z) {
-    if (kind == 1) return;
-    if (kind == 2) {  // alpha = +pi/2
-        const V3 t = Y;
-        Y = Z;
-        Z = neg(t);
-    } else if (kind == 3) {  // alpha = -pi/2
-        const V3 t = Y;
-        Y = neg(Z);
-        Z = t;
-    } else {
-        const V3 Yn = axpy(sa, Z, ca * Y);
-        const V3 Zn = axpy(-sa, Y, ca * Z);
-        Y = Yn;
-        Z = Zn;
-    }
-}
-
-// Frame i-1 -> frame i for joint i at sin / cos (s, c) of theta_i + offset_i.
-__device__ __forceinline__ void dh_advance(const DevRobot* __restrict__ rb, int i, float s, float c, Frame& T) {
-    const int kind = rb->akind[i];
-    if (rb->conv == 0) {
-        if (kind == 1)
-            T.p = axpy(rb->pz[i], T.Z, axpy(rb->px[i], T.X, T.p));
-        else if (kind != 0)
-            T.p = axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p));
-        else
-            T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
-        V3 Yb = T.Y, Zb = T.Z;
-        twist_x(kind, rb->ca[i], rb->sa[i], Yb, Zb);
-        const V3 Xn = axpy(s, Yb, c * T.X);
-        const V3 Yn = axpy(-s, T.X, c * Yb);
-        T.X = Xn;
-        T.Y = Yn;
-        T.Z = Zb;
-    } else {
-        const V3 Xb = axpy(s, T.Y, c * T.X);
-        V3 Yb = axpy(-s, T.X, c * T.Y);
-        T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
-        V3 Zb = T.Z;
-        twist_x(kind, rb->ca[i], rb->sa[i], Yb, Zb);
-        T.X = Xb;
-        T.Y = Yb;
-        T.Z = Zb;
-    }
-}
-
 template <int NM, bool STORE>
 __device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n, const float* th,
                                          V3* P, V3* Z, Frame& ee) {
     Frame T = identity_frame();
-    const bool std_dh = rb->conv != 0;
+    if (rb->conv == 0) {
 #pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        if (i < n) {
-            if (STORE && std_dh) {
-                P[i] = T.p;
-                Z[i] = T.Z;
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                float s, c;
+                sincos_cw(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
+                V3 Yb = axpy(sa, T.Z, ca * T.Y);
+                V3 Zb = axpy(-sa, T.Y, ca * T.Z);
+                V3 Xn = axpy(s, Yb, c * T.X);
+                V3 Yn = axpy(-s, T.X, c * Yb);
+                T.X = Xn;
+                T.Y = Yn;
+                T.Z = Zb;
+                if (STORE) {
+                    P[i] = T.p;
+                    Z[i] = T.Z;
+                }
             }
-            float s, c;
-            sincos_cw(th[i] + rb->off[i], &s, &c);
-            dh_advance(rb, i, s, c, T);
-            if (STORE && !std_dh) {
-                P[i] = T.p;
-                Z[i] = T.Z;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                if (STORE) {
+                    P[i] = T.p;
+                    Z[i] = T.Z;
+                }
+                float s, c;
+                sincos_cw(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                V3 Xb = axpy(s, T.Y, c * T.X);
+                V3 Yb = axpy(-s, T.X, c * T.Y);
+                T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
+                V3 Yn = axpy(sa, T.Z, ca * Yb);
+                V3 Zn = axpy(-sa, Yb, ca * T.Z);
+                T.X = Xb;
+                T.Y = Yn;
+                T.Z = Zn;
             }
         }
     }
@@ -192,7 +166,26 @@ __device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int 
                                            Frame& T) {
     float s, c;
     sincos_cw(theta + rb->off[i], &s, &c);
-    dh_advance(rb, i, s, c, T);
+    const float ca = rb->ca[i], sa = rb->sa[i];
+    if (rb->conv == 0) {
+        T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
+        V3 Yb = axpy(sa, T.Z, ca * T.Y);
+        V3 Zb = axpy(-sa, T.Y, ca * T.Z);
+        V3 Xn = axpy(s, Yb, c * T.X);
+        V3 Yn = axpy(-s, T.X, c * Yb);
+        T.X = Xn;
+        T.Y = Yn;
+        T.Z = Zb;
+    } else {
+        V3 Xb = axpy(s, T.Y, c * T.X);
+        V3 Yb = axpy(-s, T.X, c * T.Y);
+        T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
+        V3 Yn = axpy(sa, T.Z, ca * Yb);
+        V3 Zn = axpy(-sa, Yb, ca * T.Z);
+        T.X = Xb;
+        T.Y = Yn;
+        T.Z = Zn;
+    }
 }
 
 // Rotation -> unit quaternion, Shepperd's method (largest of trace and the

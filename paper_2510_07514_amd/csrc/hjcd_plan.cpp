@@ -73,7 +73,7 @@ void plan_free(hjcd_plan p) {
     if (p->main) (void)hipStreamDestroy(p->main);
 }
 
-SolveArgs solve_args(hjcd_plan p, int ri) {
+SolveArgs solve_args(hjcd_plan p, int ri, int stage) {
     SolveArgs a{};
     a.rb = p->robots[ri]->dev;
     a.n = p->robots[ri]->n;
@@ -90,21 +90,22 @@ SolveArgs solve_args(hjcd_plan p, int ri) {
     a.map = m;
     a.S = p->S;
     a.targets = p->targets;
+    // stage 0: PO-CCD, 1: PJ-IK on the CD results
     const bool gathered = p->seeds && !p->grp.identity;
-    a.q_in = gathered ? p->qw : p->seeds;
+    a.q_in = stage == 1 || gathered ? p->qw : p->seeds;
     a.q_in_stride = p->S;
     a.q_out = p->qw;
     a.err_p = p->ep;
     a.err_o = p->eo;
     a.cost = p->cost;
     a.traj = nullptr;
-    a.init_mode = p->seeds ? INIT_LOAD : INIT_UNIFORM;
-    a.do_cd = 1;
-    a.do_polish = 1;
+    a.init_mode = (stage == 1 || p->seeds) ? INIT_LOAD : INIT_UNIFORM;
+    a.do_cd = stage == 0;
+    a.do_polish = stage == 1;
     a.kp = p->kp;
     a.counters = nullptr;
     a.variant = p->choice[ri].variant;
-    a.block_threads = p->choice[ri].block_threads;
+    a.block_threads = stage == 1 ? p->choice[ri].block_threads : 256;
     return a;
 }
 
@@ -134,7 +135,8 @@ hjcd_status enqueue(hjcd_plan p, hipStream_t st) {
     for (int ri = 0; ri < p->n_robots; ++ri) {
         if (p->choice[ri].seeds == 0) continue;
         HIP_TRY(hipStreamWaitEvent(p->side[ri], p->fork, 0));
-        HIP_TRY(launch_solve(solve_args(p, ri), p->side[ri]));
+        HIP_TRY(launch_solve(solve_args(p, ri, 0), p->side[ri]));
+        HIP_TRY(launch_solve(solve_args(p, ri, 1), p->side[ri]));
         HIP_TRY(launch_collide(collide_args(p, ri), p->side[ri]));
         HIP_TRY(hipEventRecord(p->join[ri], p->side[ri]));
         HIP_TRY(hipStreamWaitEvent(st, p->join[ri], 0));
@@ -164,20 +166,25 @@ hjcd_status enqueue(hjcd_plan p, hipStream_t st) {
     return HJCD_OK;
 }
 
-// Time each candidate launch shape of robot ri's solve kernel on the plan's
-// buffers (one warm-up and two timed launches) and keep the fastest.
-hjcd_status autotune(hjcd_plan p, int ri) {
+// Time each candidate launch shape of robot ri's PJ-IK kernel (the variant
+// and workgroup size apply to it; PO-CCD keeps the default shape) on the
+// plan's buffers, one warm-up and two timed launches, and keep the fastest.
+hjcd_status autotune(hjcd_plan p, int ri, float* qs) {
     static const int kBlocks[] = {64, 128, 256};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     hjcd_tune_choice best = p->choice[ri];
     best.ms = 3.4e38f;
+    // PO-CCD once; every timed PJ-IK launch then polishes the same CD
+    // results (read from qw) into the scratch rows `qs`
+    HIP_TRY(launch_solve(solve_args(p, ri, 0), p->main));
     for (int v = 0; v < 2; ++v) {
         for (int bt : kBlocks) {
             p->choice[ri].variant = v;
             p->choice[ri].block_threads = bt;
-            const SolveArgs a = solve_args(p, ri);
+            SolveArgs a = solve_args(p, ri, 1);
+            a.q_out = qs;
             HIP_TRY(launch_solve(a, p->main));
             HIP_TRY(hipEventRecord(e0, p->main));
             for (int r = 0; r < 2; ++r) HIP_TRY(launch_solve(a, p->main));
@@ -299,8 +306,13 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
             launch_gather(p->n_max, T, p->d_coffs, p->d_voffs, p->d_perm, p->S, p->S, p->seeds, p->qw, p->main) !=
                 hipSuccess)
             return bail(fail(HJCD_E_DEVICE, "seed gather failed"));
-        for (int ri = 0; ri < n_robots; ++ri)
-            if (p->choice[ri].seeds > 0 && (s = autotune(p, ri)) != HJCD_OK) return bail(s);
+        float* qs = nullptr;
+        if ((s = dalloc(&qs, (size_t)p->n_max * S1)) != HJCD_OK) return bail(s);
+        for (int ri = 0; ri < n_robots && s == HJCD_OK; ++ri)
+            if (p->choice[ri].seeds > 0) s = autotune(p, ri, qs);
+        (void)hipStreamSynchronize(p->main);
+        (void)hipFree(qs);
+        if (s != HJCD_OK) return bail(s);
     }
     // capture
     if (hipStreamBeginCapture(p->main, hipStreamCaptureModeThreadLocal) != hipSuccess)

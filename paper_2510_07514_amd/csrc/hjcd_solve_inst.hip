@@ -30,9 +30,8 @@ struct SolveOcc {
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
-template <int NM, int V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
-    SolveArgs a) {
+template <int NM>
+__device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool do_polish) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
     const int n = kExactN ? HJCD_NM : a.n;
@@ -59,17 +58,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
     }
     Counters cnt;
     Err e{};
-    if (a.do_cd) {
+    if (do_cd) {
         bool frozen = !live;
         po_ccd<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s, 0, a.kp.cd_sweeps,
                    e);
     }
-    if (a.do_polish) {
+    if (do_polish) {
         bool frozen = !live;
-        pj_ik<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.do_cd ? nullptr : a.traj, a.S, sl.s,
+        pj_ik<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
                   0, a.kp.polish_iters, e);
     }
-    if (!a.do_cd && !a.do_polish && a.targets) {
+    if (!do_cd && !do_polish && a.targets) {
         Frame ee;
         V3 Pd[1], Zd[1];
         fk_chain<NM, false>(a.rb, n, th, Pd, Zd, ee);
@@ -85,6 +84,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
         if (a.cost) a.cost[sl.s] = cost_of(e);
     }
     flush_counters(cnt, a.counters, a.counters != nullptr);
+}
+
+// Both stages as the arguments say (the stage entry points, resampling).
+template <int NM, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
+    SolveArgs a) {
+    solve_body<NM>(a, a.do_cd != 0, a.do_polish != 0);
+}
+
+// PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
+// kernel compiled for its stage alone.
+template <int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, 0>::waves))) void k_cd(SolveArgs a) {
+    solve_body<NM>(a, true, false);
+}
+
+template <int NM, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish(
+    SolveArgs a) {
+    solve_body<NM>(a, false, true);
 }
 
 // ----------------------------------------------------------------------------
@@ -160,7 +179,15 @@ template <>
 hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     const int bt = a.block_threads > 0 ? a.block_threads : 256;
     const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
-    if (a.variant == 1)
+    const bool cd_only = a.do_cd && !a.do_polish && !a.traj;
+    const bool pol_only = !a.do_cd && a.do_polish && !a.traj;
+    if (cd_only)
+        hipLaunchKernelGGL((k_cd<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
+    else if (pol_only && a.variant == 1)
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
+    else if (pol_only)
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
+    else if (a.variant == 1)
         hipLaunchKernelGGL((k_solve<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
     else
         hipLaunchKernelGGL((k_solve<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);

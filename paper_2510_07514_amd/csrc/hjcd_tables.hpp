@@ -23,7 +23,6 @@ struct alignas(16) DevRobot {
     float off[HJCD_MAX_DOF], lo[HJCD_MAX_DOF], hi[HJCD_MAX_DOF];
     float ca[HJCD_MAX_DOF], sa[HJCD_MAX_DOF], a[HJCD_MAX_DOF], d[HJCD_MAX_DOF];
     float px[HJCD_MAX_DOF], py[HJCD_MAX_DOF], pz[HJCD_MAX_DOF];  // modified DH: (a, -d sa, d ca)
-    int32_t akind[HJCD_MAX_DOF];  // twist: 1 alpha = 0, 2 alpha = +pi/2, 3 alpha = -pi/2, 0 other
     float tool[12];                                            // row-major 3 x 4
     // per link (0..n): spheres sorted by link
     int32_t link_first[kMaxLinks], link_count[kMaxLinks];

@@ -1,0 +1,139 @@
+"""GPU edge cases of the whole solve through the C ABI, against the oracle:
+ragged and empty seed counts, top-k beyond the seed count, an empty batch,
+the smallest and the largest chains, and a seed that already solves its
+target."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_common import say
+from paper_2510_07514_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_07514_amd import hjcd
+    return hjcd
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.hjcd_ctx_create(0)
+    yield c
+    c.close()
+
+
+def _solve(H, ctx, rob, scene, tg, offs, params, seeds=None):
+    import torch
+    T, k, n = len(tg), params["top_k"], rob.dof
+    o = dict(q=torch.zeros(max(T * k, 1), n, device="cuda"), ep=torch.zeros(max(T * k, 1), device="cuda"),
+             eo=torch.zeros(max(T * k, 1), device="cuda"),
+             fl=torch.zeros(max(T * k, 1), dtype=torch.uint8, device="cuda"),
+             nf=torch.zeros(max(T, 1), dtype=torch.int32, device="cuda"),
+             sv=torch.zeros(max(T, 1), dtype=torch.uint8, device="cuda"))
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, scene.spheres, scene.boxes)
+    targets = torch.as_tensor(np.ascontiguousarray(np.asarray(tg, np.float32).reshape(-1, 7).T)).cuda() if T else \
+        torch.zeros(7, 1, device="cuda")
+    sd = None if seeds is None else torch.as_tensor(np.ascontiguousarray(seeds, np.float32)).cuda()
+    H.hjcd_solve(ctx, [rb], sc, targets, offs, H.params_from_dict(params), o["q"], o["ep"], o["eo"], o["fl"],
+                 o["nf"], o["sv"], seeds=sd)
+    torch.cuda.synchronize()
+    return {kk: v.cpu().numpy() for kk, v in o.items()}
+
+
+def _check_against_oracle(rob, scene, tg, offs, params, g, max_disagree=0, seeds=None):
+    T, k, n = len(tg), params["top_k"], rob.dof
+    ref = O.solve(rob, scene, np.asarray(tg, np.float64), offs, params,
+                  seeds=None if seeds is None else seeds[:n].T.astype(np.float64))
+    disagree = int(np.sum(g["sv"][:T] != ref["solved"]))
+    say(f"  solved gpu {g['sv'][:T].tolist()} oracle {ref['solved'].tolist()}")
+    assert disagree <= max_disagree
+    for t in range(T):
+        M = int(offs[t + 1] - offs[t])
+        for r in range(k):
+            slot = t * k + r
+            if r >= M:
+                # fewer seeds than k: the remaining slots are empty
+                assert g["fl"][slot] == 255 and np.isinf(g["ep"][slot])
+                continue
+            assert g["fl"][slot] in (0, 1)
+            f = O.fk(rob, g["q"][slot].astype(np.float64))
+            e = O.residual(np.asarray(tg[t][:3], np.float64), np.asarray(tg[t][3:], np.float64), f["p_ee"],
+                           f["R_ee"])
+            assert abs(np.linalg.norm(e["rp"]) - g["ep"][slot]) < 2e-5
+        assert g["nf"][t] <= M
+    return ref
+
+
+def test_ragged_and_empty_targets(H, ctx):
+    """Seed counts 0, 1, 63, 64, 65, 130 in one batch (waves straddle targets,
+    a target with no seeds), top-4."""
+    say("case: ragged and empty seed counts")
+    b = W.config_tiny(host_seeds=False)
+    rob = b.robots[0]
+    counts = np.array([0, 1, 63, 64, 65, 130])
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    tg = O.targets_from_qstar(rob, b.q_star[:6])
+    params = dict(b.params, top_k=4)
+    g = _solve(H, ctx, rob, b.scene, tg, offs, params)
+    assert g["sv"][0] == 0 and g["nf"][0] == 0 and np.all(g["fl"][0:4] == 255)
+    _check_against_oracle(rob, b.scene, tg, offs, params, g, max_disagree=1)
+
+
+def test_empty_batch_is_a_no_op(H, ctx):
+    say("case: T = 0")
+    b = W.config_tiny(host_seeds=False)
+    g = _solve(H, ctx, b.robots[0], b.scene, np.zeros((0, 7), np.float32), np.zeros(1, np.int64), b.params)
+    assert g["sv"].shape == (1,)
+
+
+def test_one_joint_chain(H, ctx):
+    """A single revolute joint with a 0.5 m link: every target on its circle
+    is reachable exactly in position and orientation."""
+    say("case: 1-DoF chain")
+    rob = W.planar_chain([0.5], limit=3.0)
+    rng = np.random.default_rng(5)
+    qs = rng.uniform(-3, 3, size=(6, 1)).astype(np.float32)
+    tg = O.targets_from_qstar(rob, qs)
+    offs = np.arange(7, dtype=np.int64) * 64
+    params = W.default_params(top_k=2, rng_seed=9)
+    g = _solve(H, ctx, rob, W.empty_scene(), tg, offs, params)
+    assert g["sv"].sum() == 6
+    _check_against_oracle(rob, W.empty_scene(), tg, offs, params, g)
+    best = g["q"].reshape(6, 2, 1)[:, 0, 0]
+    assert np.all(np.abs(best - qs[:, 0]) < 1e-3)
+
+
+def test_thirty_two_joint_chain(H, ctx):
+    """The largest chain the ABI takes (32 joints, the 32-joint bucket)."""
+    say("case: 32-DoF chain")
+    rng = np.random.default_rng(32)
+    rob = W.random_chain(rng, 32, "random32")
+    tg = O.targets_from_qstar(rob, W.uniform_configs(rng, rob, 4))
+    offs = np.arange(5, dtype=np.int64) * 96
+    params = W.default_params(top_k=2, rng_seed=3, cd_sweeps=10, polish_iters=10)
+    g = _solve(H, ctx, rob, W.empty_scene(), tg, offs, params)
+    _check_against_oracle(rob, W.empty_scene(), tg, offs, params, g, max_disagree=1)
+
+
+def test_seed_that_already_solves(H, ctx):
+    """Seed 0 of each target is its q*: it passes both exit tests before the
+    first iteration, so a collision-free one solves its target."""
+    say("case: converged seed")
+    b = W.config_tiny(host_seeds=True)
+    rob = b.robots[0]
+    seeds = b.seeds.copy()
+    for t in range(b.T):
+        seeds[:rob.dof, t * 64] = np.asarray(b.q_star[t], np.float32)
+    tg = O.targets_from_qstar(rob, b.q_star)
+    g = _solve(H, ctx, rob, b.scene, tg, b.seed_offsets, b.params, seeds=seeds)
+    ref = _check_against_oracle(rob, b.scene, tg, b.seed_offsets, b.params, g, max_disagree=0, seeds=seeds)
+    for t in range(b.T):
+        if ref["flag_seed"][t * 64] == 0:
+            assert g["sv"][t] == 1 and g["ep"][t] < 1e-5
