@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libhjcd.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 ARCH = "gfx950"
-NM_BUCKETS = (6, 7, 8, 16, 24, 32)  # 6 and 7: exact joint counts
+NM_BUCKETS = (6, 7, 8, 12, 16, 20, 24, 32)  # 6 and 7: exact joint counts
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

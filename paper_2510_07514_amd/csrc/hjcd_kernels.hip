@@ -448,15 +448,27 @@ static inline unsigned blocks_for(int64_t count, int per) { return (unsigned)((c
         }                         \
     } while (0)
 
-// The per-seed solve kernels also come as exact 6- and 7-joint instances.
+// The per-seed solve kernels come in finer buckets: exact 6- and 7-joint
+// instances, then bounds 8, 12, 16, 20, 24, 32 (a bucket's arrays take
+// registers for all its joints, so the padding costs occupancy).
 #define HJCD_DISPATCH_SOLVE(n, CALL) \
     do {                             \
         if ((n) == 6) {              \
             CALL(6);                 \
         } else if ((n) == 7) {       \
             CALL(7);                 \
+        } else if ((n) <= 8) {       \
+            CALL(8);                 \
+        } else if ((n) <= 12) {      \
+            CALL(12);                \
+        } else if ((n) <= 16) {      \
+            CALL(16);                \
+        } else if ((n) <= 20) {      \
+            CALL(20);                \
+        } else if ((n) <= 24) {      \
+            CALL(24);                \
         } else {                     \
-            HJCD_DISPATCH_NM(n, CALL); \
+            CALL(32);                \
         }                            \
     } while (0)
 

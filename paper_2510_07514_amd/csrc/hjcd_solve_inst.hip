@@ -17,14 +17,15 @@ namespace hjcd {
 // takes exactly n registers per joint array.
 constexpr bool kExactN = HJCD_NM < 8;
 
-// Occupancy variants of the per-seed solve kernel (a launch-shape choice of
-// the autotuner; the arithmetic is the same).  Variant 0: three waves per
-// SIMD for chains of up to 8 joints (at most 168 VGPRs, a few spills, faster
-// than the two waves of the unconstrained allocation), the compiler's choice
-// above.  Variant 1: at least two waves per SIMD (at most 256 VGPRs).
+// Occupancy variants of the per-seed solve kernels (a launch-shape choice of
+// the autotuner; the arithmetic is the same).  Minimum waves per SIMD:
+//   NM <= 8:       variant 0: 3 (at most 168 VGPRs, a few spills; faster than
+//                  the two waves of the unconstrained ~200), variant 1: 2
+//   8 < NM <= 16:  variant 0: 2 (at most 256 VGPRs), variant 1: 1 (as allocated)
+//   NM > 16:       variant 0: 1 (as allocated), variant 1: 2 (with spills)
 template <int NM, int V>
 struct SolveOcc {
-    static constexpr int waves = V == 0 ? (NM <= 8 ? 3 : 1) : 2;
+    static constexpr int waves = NM <= 8 ? (V == 0 ? 3 : 2) : NM <= 16 ? (V == 0 ? 2 : 1) : (V == 0 ? 1 : 2);
 };
 
 // ----------------------------------------------------------------------------
