@@ -631,12 +631,34 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
 
-// In place: A (lower, packed) -> L with A = L L^T.  Returns false if a pivot
-// is not positive.  The 6 x 6 systems are assembled and factored in double
-// precision: near singular J their condition number (up to ~|J|^2 / lambda)
-// is beyond what single precision resolves, and double FMAs issue at the same
-// per-lane rate as unpacked single ones on CDNA4.
-__device__ __forceinline__ bool chol6(double* A) {
+// The 6 x 6 systems are assembled and factored in double precision: near
+// singular J their condition number (up to ~|J|^2 / lambda) is beyond what
+// single precision resolves, and double FMAs issue at the same per-lane rate
+// as unpacked single ones on CDNA4.
+//
+// 1/sqrt(s) and 1/d in double precision from the single-precision hardware
+// estimates (relative error ~2^-22) and two Newton steps each (quadratic
+// convergence: ~2^-44, then rounding-limited), a few FMAs instead of the
+// library's division and square-root sequences.  Arguments are the positive
+// pivots and column norms of the 6 x 6 systems (>= lambda > 0).
+__device__ __forceinline__ double rsqrt_nr(double s) {
+    double r = (double)rsqrtf((float)fmax(s, 1e-30));
+    const double hs = 0.5 * s;
+    r = r * fma(-hs * r, r, 1.5);
+    r = r * fma(-hs * r, r, 1.5);
+    return r;
+}
+
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = (double)(1.f / (float)d);
+    r = r * fma(-d, r, 2.0);
+    r = r * fma(-d, r, 2.0);
+    return r;
+}
+
+// In place: A (lower, packed) -> L with A = L L^T, and the reciprocals of
+// L's diagonal in inv.  Returns false if a pivot is not positive.
+__device__ __forceinline__ bool chol6(double* A, double* inv) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -644,9 +666,9 @@ __device__ __forceinline__ bool chol6(double* A) {
 #pragma unroll
         for (int k = 0; k < j; ++k) s = fma(-A[tri(j, k)], A[tri(j, k)], s);
         ok = ok && (s > 0.0);
-        const double l = sqrt(fmax(s, 1e-300));
-        const double il = 1.0 / l;
-        A[tri(j, j)] = l;
+        const double il = rsqrt_nr(fmax(s, 1e-300));
+        A[tri(j, j)] = s * il;
+        inv[j] = il;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double t = A[tri(i, j)];
@@ -658,21 +680,21 @@ __device__ __forceinline__ bool chol6(double* A) {
     return ok;
 }
 
-__device__ __forceinline__ void chol6_solve(const double* L, const double* b, double* x) {
+__device__ __forceinline__ void chol6_solve(const double* L, const double* inv, const double* b, double* x) {
     double y[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double t = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) t = fma(-L[tri(i, k)], y[k], t);
-        y[i] = t / L[tri(i, i)];
+        y[i] = t * inv[i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double t = y[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) t = fma(-L[tri(k, i)], x[k], t);
-        x[i] = t / L[tri(i, i)];
+        x[i] = t * inv[i];
     }
 }
 
@@ -766,7 +788,7 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                             cd[r] = (double)c[r];
                             dj = fma(cd[r], cd[r], dj);
                         }
-                        const double idj = 1.0 / dj;
+                        const double idj = rcp_nr(dj);
 #pragma unroll
                         for (int a = 0; a < 6; ++a) {
                             const double ca = cd[a] * idj;
@@ -780,11 +802,12 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
 #pragma unroll
                     for (int b = 0; b <= a; ++b)
                         A[tri(a, b)] = A[tri(a, b)] * ((double)w6[a] * (double)w6[b]) + (a == b ? (double)kp.lam : 0.0);
-                chol6(A);
+                double inv[6];
+                chol6(A, inv);
                 double rhs[6], yd[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) rhs[r] = (double)w6[r] * (double)e6[r];
-                chol6_solve(A, rhs, yd);
+                chol6_solve(A, inv, rhs, yd);
                 float y[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) y[r] = (float)(yd[r] * (double)w6[r]);
@@ -868,11 +891,12 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
                 }
 #pragma unroll
                 for (int a = 0; a < 6; ++a) A[tri(a, a)] += (double)kp.lambda_gn;
-                chol6(A);
+                double inv[6];
+                chol6(A, inv);
                 double ed[6], yd[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) ed[r] = (double)e6[r];
-                chol6_solve(A, ed, yd);
+                chol6_solve(A, inv, ed, yd);
                 float y[6];
 #pragma unroll
                 for (int r = 0; r < 6; ++r) y[r] = (float)yd[r];
