@@ -718,11 +718,117 @@ __device__ __forceinline__ float trial_cost(const DevRobot* __restrict__ rb, int
 }
 
 // ----------------------------------------------------------------------------
-// PJ-IK (Alg. PJ-IK, Sec. IV-B) on one seed.
+// PJ-IK line search with the later trials spread over the wave.
+//
+// The first trial (alpha = 1) runs on every lane that still searches.  The
+// lanes it did not satisfy need alpha = 1/beta, ..., 1/beta^A in order and
+// take the first that lowers the cost.  Those trials are independent, so they
+// are evaluated all at once as (lane, alpha) tasks dealt to every lane of the
+// wave (converged and satisfied lanes included), 64 tasks per pass; each
+// searching lane then takes its first decreasing alpha.  The trial values and
+// costs are the ones the sequential search computes, so the choice is the
+// same; the wave runs ceil(searching lanes x A / 64) passes instead of A.
+// Counters record the trials the sequential search would run.
+// ----------------------------------------------------------------------------
+constexpr int kLsSpread = 8;  // largest A handled this way
+
+// Lane index of the r-th set bit of m (r < popcount(m)): binary descent
+// over halves of the 64-bit mask.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = m & ((1ull << w) - 1ull);
+        const int c = __popcll(low);
+        const bool up = r >= c;
+        r = up ? r - c : r;
+        m = up ? (m >> w) : low;
+        pos += up ? w : 0;
+    }
+    return pos;
+}
+
+template <int NM>
+__device__ __forceinline__ void line_search_spread(const DevRobot* __restrict__ rb, int n, const Target& tg,
+                                                   const KParams& kp, float* th, const float* dth, float* tt,
+                                                   float c0, bool& done, Counters& cnt) {
+    // alpha = 1 on the searching lanes
+    if (!wave_all(done)) {
+        if (!done) {
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) tt[j] = clampf(fmaf(1.f, dth[j], th[j]), rb->lo[j], rb->hi[j]);
+            const float c1 = trial_cost<NM>(rb, n, tg, tt);
+            ++cnt.pol_trials;
+            if (c1 < c0) {
+#pragma unroll
+                for (int j = 0; j < NM; ++j)
+                    if (j < n) th[j] = tt[j];
+                done = true;
+            }
+        }
+    }
+    const int A = kp.ls_A;
+    const uint64_t need = __ballot(!done);
+    if (A == 0 || need == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int ntask = __popcll(need) * A;
+    const int myrank = __popcll(need & ((1ull << lane) - 1ull));
+    uint32_t lower = 0u;  // bit k: trial k + 1 lowers this lane's cost
+    for (int base = 0; base < ntask; base += 64) {
+        const int t = base + lane;
+        const bool has = t < ntask;
+        const int r = has ? t / A : 0;
+        const int i = has ? 1 + t - r * A : 1;  // trial index 1..A
+        const int L = nth_set_bit(need, r);
+        // alpha_i as the sequential search forms it: i products by 1/beta
+        float a = 1.f;
+#pragma unroll
+        for (int k = 1; k <= kLsSpread; ++k)
+            if (k <= i) a *= kp.inv_beta;
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            const float thL = __shfl(th[j], L, 64);
+            const float dL = __shfl(dth[j], L, 64);
+            if (j < n) tt[j] = clampf(fmaf(a, dL, thL), rb->lo[j], rb->hi[j]);
+        }
+        Target tgL;
+        tgL.p = mk(__shfl(tg.p.x, L, 64), __shfl(tg.p.y, L, 64), __shfl(tg.p.z, L, 64));
+        tgL.q = Quat{__shfl(tg.q.w, L, 64), __shfl(tg.q.x, L, 64), __shfl(tg.q.y, L, 64), __shfl(tg.q.z, L, 64)};
+        float c = 3.4e38f;
+        if (has) c = trial_cost<NM>(rb, n, tgL, tt);
+        // each searching lane collects its tasks dealt in this pass
+#pragma unroll
+        for (int k = 0; k < kLsSpread; ++k) {
+            const int tk = myrank * A + k;
+            const bool mine = k < A && tk >= base && tk < base + 64;
+            const float v = __shfl(c, mine ? tk - base : lane, 64);
+            if (!done && mine && v < c0) lower |= 1u << k;
+        }
+    }
+    if (!done) {
+        const int first = lower ? __builtin_ctz(lower) : -1;
+        cnt.pol_trials += first >= 0 ? (uint32_t)(first + 1) : (uint32_t)A;
+        if (first >= 0) {
+            float a = 1.f;
+#pragma unroll
+            for (int k = 1; k <= kLsSpread; ++k)
+                if (k <= first + 1) a *= kp.inv_beta;
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) th[j] = clampf(fmaf(a, dth[j], th[j]), rb->lo[j], rb->hi[j]);
+            done = true;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// PJ-IK (Alg. PJ-IK, Sec. IV-B) on one seed.  SPREAD selects the spread
+// line search above (same results; fewer passes, more live registers).
 // LM step: (J^T W^2 J + lam D) dtheta = J^T W^2 e is solved in its 6 x 6
 // push-through form dtheta = D^-1 J^T W (W J D^-1 J^T W + lam I)^-1 W e.
 // ----------------------------------------------------------------------------
-template <int NM>
+template <int NM, bool SPREAD = true>
 __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
                                       uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
                                       Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
@@ -830,23 +936,27 @@ __device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, co
             write_traj<NM>(traj, n, S, s, it, th, last_ep, last_phi);
         }
         // --- backtracking line search (eq. line-search), first decreasing alpha
-        float alpha = 1.f;
-        for (int i = 0; i <= kp.ls_A; ++i) {
-            if (wave_all(done)) break;
-            if (!done) {
-#pragma unroll
-                for (int j = 0; j < NM; ++j)
-                    if (j < n) tt[j] = clampf(fmaf(alpha, dth[j], th[j]), rb->lo[j], rb->hi[j]);
-                const float c1 = trial_cost<NM>(rb, n, tg, tt);
-                ++cnt.pol_trials;
-                if (c1 < c0) {
+        if (SPREAD && kp.ls_A <= kLsSpread) {
+            line_search_spread<NM>(rb, n, tg, kp, th, dth, tt, c0, done, cnt);
+        } else {
+            float alpha = 1.f;
+            for (int i = 0; i <= kp.ls_A; ++i) {
+                if (wave_all(done)) break;
+                if (!done) {
 #pragma unroll
                     for (int j = 0; j < NM; ++j)
-                        if (j < n) th[j] = tt[j];
-                    done = true;
+                        if (j < n) tt[j] = clampf(fmaf(alpha, dth[j], th[j]), rb->lo[j], rb->hi[j]);
+                    const float c1 = trial_cost<NM>(rb, n, tg, tt);
+                    ++cnt.pol_trials;
+                    if (c1 < c0) {
+#pragma unroll
+                        for (int j = 0; j < NM; ++j)
+                            if (j < n) th[j] = tt[j];
+                        done = true;
+                    }
                 }
+                alpha *= kp.inv_beta;
             }
-            alpha *= kp.inv_beta;
         }
         // --- dogleg fallback (eq. dogleg)
         if (!wave_all(done)) {

@@ -26,12 +26,15 @@ constexpr bool kExactN = HJCD_NM < 8;
 template <int NM, int V>
 struct SolveOcc {
     static constexpr int waves = NM <= 8 ? (V == 0 ? 3 : 2) : NM <= 16 ? (V == 0 ? 2 : 1) : (V == 0 ? 1 : 2);
+    // the spread line search needs ~50 more live registers: at three waves per
+    // SIMD they would spill, so that variant keeps the sequential search
+    static constexpr bool spread = !(NM <= 8 && V == 0);
 };
 
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
-template <int NM>
+template <int NM, bool SPREAD>
 __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool do_polish) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
@@ -66,7 +69,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     }
     if (do_polish) {
         bool frozen = !live;
-        pj_ik<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
+        pj_ik<NM, SPREAD>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
                   0, a.kp.polish_iters, e);
     }
     if (!do_cd && !do_polish && a.targets) {
@@ -91,20 +94,20 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
     SolveArgs a) {
-    solve_body<NM>(a, a.do_cd != 0, a.do_polish != 0);
+    solve_body<NM, SolveOcc<NM, V>::spread>(a, a.do_cd != 0, a.do_polish != 0);
 }
 
 // PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
 // kernel compiled for its stage alone.
 template <int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, 0>::waves))) void k_cd(SolveArgs a) {
-    solve_body<NM>(a, true, false);
+    solve_body<NM, false>(a, true, false);
 }
 
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish(
     SolveArgs a) {
-    solve_body<NM>(a, false, true);
+    solve_body<NM, SolveOcc<NM, V>::spread>(a, false, true);
 }
 
 // ----------------------------------------------------------------------------
@@ -144,7 +147,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
         if (frozen) st |= SLOT_CD_FROZEN;
     } else {
         bool frozen = !live || (st & SLOT_POL_FROZEN);
-        pj_ik<NM>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er);
+        pj_ik<NM, SolveOcc<NM, 0>::spread>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0,
+                                          blk.k1, er);
         // the exit test of iteration k1 (or the one after the last iteration)
         // on the state this chunk leaves: a seed converged by the chunk's last
         // step is eligible for the collision check at this chunk's end
