@@ -142,6 +142,9 @@ typedef struct {
 /* Bind to HIP device `device` (must be gfx950).  HJCD_E_DEVICE when no such
  * device exists (e.g. on a host without GPUs). */
 hjcd_status hjcd_ctx_create(int device, hjcd_ctx* out);
+/* Synchronises the device and frees the context's buffers.  Robots, scenes,
+ * servers and plans created on it own their memory and may be destroyed
+ * after it (but not used with it any more). */
 void hjcd_ctx_destroy(hjcd_ctx ctx);
 const char* hjcd_last_error(void);
 void hjcd_params_default(hjcd_params* p);

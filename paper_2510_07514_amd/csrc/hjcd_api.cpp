@@ -380,6 +380,7 @@ hjcd_status hjcd_load_robot(hjcd_ctx c, const hjcd_robot_desc* d, hjcd_robot* ou
 
     hjcd_robot r = new hjcd_robot_s();
     r->ctx = c;
+    r->device = c->device;
     r->n = n;
     DevRobot& h = r->host;
     std::memset(&h, 0, sizeof(h));
@@ -473,7 +474,7 @@ hjcd_status hjcd_load_robot(hjcd_ctx c, const hjcd_robot_desc* d, hjcd_robot* ou
 
 void hjcd_robot_destroy(hjcd_robot r) {
     if (!r) return;
-    (void)hipSetDevice(r->ctx->device);
+    (void)hipSetDevice(r->device);
     (void)hipDeviceSynchronize();
     if (r->dev) (void)hipFree(r->dev);
     delete r;
@@ -502,6 +503,7 @@ hjcd_status hjcd_load_scene(hjcd_ctx c, int32_t n_sph, const float* sph, int32_t
     if ((s = bind(c)) != HJCD_OK) return s;
     hjcd_scene sc = new hjcd_scene_s();
     sc->ctx = c;
+    sc->device = c->device;
     sc->n_sph = n_sph;
     sc->n_box = n_box;
     std::vector<float> bx((size_t)8 * n_box, 0.f);
@@ -526,7 +528,7 @@ hjcd_status hjcd_load_scene(hjcd_ctx c, int32_t n_sph, const float* sph, int32_t
 
 void hjcd_scene_destroy(hjcd_scene sc) {
     if (!sc) return;
-    (void)hipSetDevice(sc->ctx->device);
+    (void)hipSetDevice(sc->device);
     (void)hipDeviceSynchronize();
     if (sc->sph) (void)hipFree(sc->sph);
     if (sc->box) (void)hipFree(sc->box);

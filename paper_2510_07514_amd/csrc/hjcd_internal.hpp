@@ -65,8 +65,12 @@ struct hjcd_ctx_s {
     hipStream_t stats_stream = nullptr;
 };
 
+// Robots, scenes, servers and plans keep their context's device id: they may
+// be destroyed after the context (their memory is their own), so their
+// destroy functions never read the context.
 struct hjcd_robot_s {
     hjcd_ctx ctx = nullptr;
+    int device = 0;
     hjcd::DevRobot host;
     hjcd::DevRobot* dev = nullptr;
     int n = 0;
@@ -74,6 +78,7 @@ struct hjcd_robot_s {
 
 struct hjcd_scene_s {
     hjcd_ctx ctx = nullptr;
+    int device = 0;
     float* sph = nullptr;
     int32_t n_sph = 0;
     float* box = nullptr;

@@ -15,6 +15,7 @@ using namespace hjcd;
 
 struct hjcd_plan_s {
     hjcd_ctx ctx = nullptr;
+    int device = 0;
     int32_t n_robots = 0;
     hjcd_robot robots[HJCD_MAX_ROBOTS] = {};
     hjcd_scene scene = nullptr;
@@ -242,6 +243,7 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
         return st;
     };
     p->ctx = c;
+    p->device = c->device;
     p->n_robots = n_robots;
     for (int i = 0; i < n_robots; ++i) p->robots[i] = robots[i];
     p->scene = sc;
@@ -334,7 +336,7 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
 
 hjcd_status hjcd_plan_execute(hjcd_plan p, void* stream) {
     if (!p) return fail(HJCD_E_INVALID, "plan is NULL");
-    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipSetDevice(p->device));
     HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
     return HJCD_OK;
 }
@@ -348,7 +350,7 @@ hjcd_status hjcd_plan_choice(hjcd_plan p, int32_t robot, hjcd_tune_choice* out) 
 
 void hjcd_plan_destroy(hjcd_plan p) {
     if (!p) return;
-    (void)hipSetDevice(p->ctx->device);
+    (void)hipSetDevice(p->device);
     if (p->main) (void)hipStreamSynchronize(p->main);
     (void)hipDeviceSynchronize();
     plan_free(p);

@@ -92,6 +92,7 @@ T* dev_alloc(size_t count, bool& ok) {
 
 struct hjcd_server_s {
     hjcd_ctx ctx = nullptr;
+    int device = 0;
     hjcd_robot robot = nullptr;
     hjcd_scene scene = nullptr;
     hjcd_params params{};
@@ -480,7 +481,7 @@ hjcd_status plain_step(hjcd_server s) {
 }
 
 void worker_main(hjcd_server s) {
-    (void)hipSetDevice(s->ctx->device);
+    (void)hipSetDevice(s->device);
     while (!s->stop.load()) {
         bool idle;
         {
@@ -545,6 +546,7 @@ hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene,
     if (C < 64) return fail(HJCD_E_NOMEM, "memory budget holds less than one 64-slot block");
     auto* srv = new hjcd_server_s();
     srv->ctx = ctx;
+    srv->device = ctx->device;
     srv->robot = robot;
     srv->scene = scene;
     srv->params = *params;
@@ -716,7 +718,7 @@ void hjcd_server_destroy(hjcd_server srv) {
     srv->stop.store(true);
     srv->cv.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
-    (void)hipSetDevice(srv->ctx->device);
+    (void)hipSetDevice(srv->device);
     if (srv->stream) (void)hipStreamSynchronize(srv->stream);
     server_free(srv);
     delete srv;

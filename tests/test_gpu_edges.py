@@ -137,3 +137,19 @@ def test_seed_that_already_solves(H, ctx):
     for t in range(b.T):
         if ref["flag_seed"][t * 64] == 0:
             assert g["sv"][t] == 1 and g["ep"][t] < 1e-5
+
+
+def test_handles_outlive_their_context(H):
+    """A robot and a scene destroyed after their context leave no HIP error
+    behind in the caller's thread (the next torch kernel launch checks)."""
+    import torch
+    say("case: robot and scene destroyed after the context")
+    b = W.config_tiny(host_seeds=False)
+    c2 = H.hjcd_ctx_create(0)
+    rb = H.hjcd_load_robot(c2, b.robots[0])
+    sc = H.hjcd_load_scene(c2, b.scene.spheres, b.scene.boxes)
+    c2.close()
+    rb.close()
+    sc.close()
+    x = torch.ones(1000, device="cuda")
+    assert float(x.sum().item()) == 1000.0
