@@ -51,20 +51,36 @@ __global__ __launch_bounds__(256) void k_fk(const DevRobot* __restrict__ rb, int
 // spheres only when some lane's coarse test hits; a wave stops as soon as
 // all its lanes collide.
 // ----------------------------------------------------------------------------
+// Link frames of the collision pass in LDS as (unit quaternion, origin):
+// 7 floats per link and lane, [link][7][64] with the lane fastest (conflict
+// free).  Rebuilding the rotation from the quaternion costs ~2e-7 relative,
+// i.e. < 1e-7 m on a sphere centre, far inside the 1e-5 m contact band.
+constexpr int kFrameFloats = 7;
+
 __device__ __forceinline__ void lds_store_frame(float* lds, int l, int lane, const Frame& T) {
-    float* b = lds + (l * 12) * 64 + lane;
-    const float v[12] = {T.X.x, T.X.y, T.X.z, T.Y.x, T.Y.y, T.Y.z, T.Z.x, T.Z.y, T.Z.z, T.p.x, T.p.y, T.p.z};
-#pragma unroll
-    for (int c = 0; c < 12; ++c) b[c * 64] = v[c];
+    float* b = lds + (l * kFrameFloats) * 64 + lane;
+    const Quat q = quat_of(T);
+    b[0] = q.w;
+    b[64] = q.x;
+    b[128] = q.y;
+    b[192] = q.z;
+    b[256] = T.p.x;
+    b[320] = T.p.y;
+    b[384] = T.p.z;
 }
 
 __device__ __forceinline__ Frame lds_load_frame(const float* lds, int l, int lane) {
-    const float* b = lds + (l * 12) * 64 + lane;
+    const float* b = lds + (l * kFrameFloats) * 64 + lane;
+    const float w = b[0], x = b[64], y = b[128], z = b[192];
+    const float x2 = x + x, y2 = y + y, z2 = z + z;
+    const float xx = x * x2, yy = y * y2, zz = z * z2;
+    const float xy = x * y2, xz = x * z2, yz = y * z2;
+    const float wx = w * x2, wy = w * y2, wz = w * z2;
     Frame T;
-    T.X = mk(b[0], b[64], b[128]);
-    T.Y = mk(b[192], b[256], b[320]);
-    T.Z = mk(b[384], b[448], b[512]);
-    T.p = mk(b[576], b[640], b[704]);
+    T.X = mk(1.f - (yy + zz), xy + wz, xz - wy);
+    T.Y = mk(xy - wz, 1.f - (xx + zz), yz + wx);
+    T.Z = mk(xz + wy, yz - wx, 1.f - (xx + yy));
+    T.p = mk(b[256], b[320], b[384]);
     return T;
 }
 
@@ -90,19 +106,19 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
                                              int64_t s, const float* __restrict__ os, int n_osph,
                                              const float* __restrict__ ob, int n_obox, uint32_t& n_coarse,
                                              uint32_t& n_fine) {
-    Frame T = identity_frame();
-    lds_store_frame(lds, 0, lane, T);
-    for (int i = 0; i < n; ++i) {
-        const float th = active ? q[(int64_t)i * q_stride + s] : 0.f;
-        chain_step(rb, i, th, T);
-        lds_store_frame(lds, i + 1, lane, T);
-    }
     bool hit = !active;
-    // environment
-    for (int l = 0; l <= n && !wave_all(hit); ++l) {
+    // environment, link by link along the chain walk (the frame is in
+    // registers); every frame is kept in LDS for the self pairs
+    Frame F = identity_frame();
+    for (int l = 0; l <= n; ++l) {
+        if (l > 0) {
+            const float th = active ? q[(int64_t)(l - 1) * q_stride + s] : 0.f;
+            chain_step(rb, l - 1, th, F);
+        }
+        if (wave_all(hit)) break;  // the self pairs are skipped too
+        lds_store_frame(lds, l, lane, F);
         const float Rc = rb->coarse[l][3];
         if (Rc < 0.f) continue;
-        const Frame F = lds_load_frame(lds, l, lane);
         const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
         const int f0 = rb->link_first[l], fc = rb->link_count[l];
         for (int o = 0; o < n_osph; ++o) {
@@ -494,7 +510,7 @@ hipError_t launch_fk(const DevRobot* rb, int n, int64_t S, const float* q, float
 
 hipError_t launch_collide(const CollideArgs& a, hipStream_t st) {
     if (a.S <= 0) return hipSuccess;
-    const size_t lds = (size_t)(a.n + 1) * 12 * 64 * sizeof(float);
+    const size_t lds = (size_t)(a.n + 1) * kFrameFloats * 64 * sizeof(float);
     hipLaunchKernelGGL(k_collide, dim3(blocks_for(a.S, 64)), dim3(64), lds, st, a);
     return hipGetLastError();
 }
@@ -511,7 +527,7 @@ hipError_t launch_serve_chunk(const ServeChunkArgs& a, hipStream_t st) {
 
 hipError_t launch_serve_check(const ServeCheckArgs& a, hipStream_t st) {
     if (a.nb <= 0) return hipSuccess;
-    const size_t lds = (size_t)(a.n + 1) * 12 * 64 * sizeof(float);
+    const size_t lds = (size_t)(a.n + 1) * kFrameFloats * 64 * sizeof(float);
     hipLaunchKernelGGL(k_serve_check, dim3(a.nb), dim3(64), lds, st, a);
     return hipGetLastError();
 }
