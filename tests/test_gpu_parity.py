@@ -504,3 +504,44 @@ def test_large_full_size_sampled(H, ctx):
             hit, md = O.collide(rob, b.scene, q[i, r].astype(np.float64))
             if abs(md) > 1e-5:
                 assert hit == int(fl[i, r]), (i, r, md)
+
+
+def test_executed_unit_counts_match_oracle(H, ctx):
+    """The executed units the kernels count (and the roofline multiplies by
+    per-unit flops) are the ones the oracle executes: CD iterations and
+    perturbations, PJ-IK iterations, trial evaluations, dogleg and
+    single-coordinate steps, perturbations, summed over the tiny batch."""
+    import torch
+    say("case: executed-unit counters vs oracle")
+    b = W.config_tiny(host_seeds=False)
+    rob = b.robots[0]
+    tg = O.targets_from_qstar(rob, b.q_star)
+    k = b.params["top_k"]
+    o = [torch.zeros(b.T * k, rob.dof, device="cuda"), torch.zeros(b.T * k, device="cuda"),
+         torch.zeros(b.T * k, device="cuda"), torch.zeros(b.T * k, dtype=torch.uint8, device="cuda"),
+         torch.zeros(b.T, dtype=torch.int32, device="cuda"), torch.zeros(b.T, dtype=torch.uint8, device="cuda")]
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    H.hjcd_solve(ctx, [rb], sc, targets_soa(tg), b.seed_offsets, H.params_from_dict(b.params, collect_stats=True),
+                 *o)
+    g = H.hjcd_get_stats(ctx)
+    ref = dict(cd_iters=0, cd_perturb=0, pol_iters=0, pol_trials=0, pol_dogleg=0, pol_single=0, pol_perturb=0)
+    p = b.params
+    for t in range(b.T):
+        for m in range(64):
+            th0 = O.uniform_seed(rob, p["rng_seed"], m, t)
+            r1 = O.cd(rob, tg[t].astype(np.float64), p, m, t, th0)
+            r2 = O.polish(rob, tg[t].astype(np.float64), p, m, t, r1["theta"])
+            s1, s2 = r1["stats"], r2["stats"]
+            ref["cd_iters"] += s1["iters_run"]
+            ref["cd_perturb"] += s1["n_perturb"]
+            ref["pol_iters"] += s2["iters_run"]
+            ref["pol_trials"] += s2["n_trials"]
+            ref["pol_dogleg"] += s2["n_dogleg"]
+            ref["pol_single"] += s2["n_single"]
+            ref["pol_perturb"] += s2["n_perturb"]
+    say(f"  gpu {[int(g[kk]) for kk in ref]} oracle {list(ref.values())}")
+    assert int(g["seeds"]) == b.T * 64
+    for kk, v in ref.items():
+        # near-tie seeds may take another branch; the totals stay within 3%
+        assert abs(int(g[kk]) - v) <= max(3, 0.03 * v), (kk, int(g[kk]), v)
