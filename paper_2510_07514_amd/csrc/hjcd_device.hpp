@@ -189,7 +189,12 @@ __device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int 
 }
 
 // Rotation -> unit quaternion, Shepperd's method (largest of trace and the
-// diagonal decides the divisor), w >= 0.
+// diagonal decides the divisor), w >= 0.  FAST: hardware square root and
+// reciprocal (1 ulp), for the collision pass's compressed link frames (a
+// residual fed to the solver's decisions keeps the correctly rounded forms:
+// a 2-4 ulp residual moved one sensitive PJ-IK trajectory out of the 1e-4
+// band).
+template <bool FAST = false>
 __device__ __forceinline__ Quat quat_of(const Frame& F) {
     const float R00 = F.X.x, R10 = F.X.y, R20 = F.X.z;
     const float R01 = F.Y.x, R11 = F.Y.y, R21 = F.Y.z;
@@ -200,9 +205,9 @@ __device__ __forceinline__ Quat quat_of(const Frame& F) {
     const bool c2 = !c0 && !c1 && R11 >= R22;
     const float big = c0 ? 1.f + tr : c1 ? 1.f + R00 - R11 - R22 : c2 ? 1.f - R00 + R11 - R22
                                                                        : 1.f - R00 - R11 + R22;
-    const float r = sqrtf(big);
+    const float r = FAST ? __builtin_amdgcn_sqrtf(big) : sqrtf(big);
     const float qb = 0.5f * r;
-    const float k = 0.5f / r;
+    const float k = FAST ? 0.5f * __builtin_amdgcn_rcpf(r) : 0.5f / r;
     const float d21 = (R21 - R12) * k, d02 = (R02 - R20) * k, d10 = (R10 - R01) * k;
     const float s01 = (R01 + R10) * k, s02 = (R02 + R20) * k, s12 = (R12 + R21) * k;
     Quat q;

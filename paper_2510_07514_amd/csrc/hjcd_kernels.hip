@@ -59,7 +59,7 @@ constexpr int kFrameFloats = 7;
 
 __device__ __forceinline__ void lds_store_frame(float* lds, int l, int lane, const Frame& T) {
     float* b = lds + (l * kFrameFloats) * 64 + lane;
-    const Quat q = quat_of(T);
+    const Quat q = quat_of<true>(T);
     b[0] = q.w;
     b[64] = q.x;
     b[128] = q.y;
