@@ -276,6 +276,18 @@ def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
         params = H.params_from_dict(s["params"])
         row = {"rate_req_s": rate, "requests": int(n_req), "targets": int(offs[-1]),
                "mean_seeds_per_target": round(float(np.mean(s["seeds_per_target"])), 1)}
+        if rate == rates[0]:
+            # warm-up: the first requests of the stream through both modes, so
+            # that kernel loading and first-touch allocation stay out of the
+            # measured windows
+            for mode in (H.HJCD_SERVE_BATCHED, H.HJCD_SERVE_PLAIN):
+                srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk)
+                for i in range(min(n_req, 32)):
+                    H.hjcd_server_submit(srv, poses[offs[i]:offs[i + 1]], int(s["seeds_per_target"][i]), int(offs[i]),
+                                         0.0)
+                H.hjcd_server_start(srv)
+                H.hjcd_server_wait(srv, 120.0)
+                srv.close()
         for mode, name in ((H.HJCD_SERVE_BATCHED, "served"), (H.HJCD_SERVE_PLAIN, "plain")):
             m = n_req if mode == H.HJCD_SERVE_BATCHED else min(n_req, plain_cap)
             srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk,
@@ -316,7 +328,7 @@ def main():
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--large", action="store_true", help="also time the 100,000 x 256 random 20-joint workload")
     ap.add_argument("--serve-rates", default="2000,10000,50000")
-    ap.add_argument("--serve-duration", type=float, default=0.25, help="seconds of each request stream")
+    ap.add_argument("--serve-duration", type=float, default=1.0, help="seconds of each request stream")
     ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
     ap.add_argument("--serve-chunk", type=int, default=4, help="iterations per serving chunk")
     ap.add_argument("--plain-cap", type=int, default=4000, help="requests of each stream the plain server runs")
