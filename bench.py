@@ -35,7 +35,7 @@ PEAK_HBM_GBS = 8000.0
 
 
 # ---------------------------------------------------------------------------
-# Algorithmic FP32 flops of the fused solve kernel per executed unit.
+# Algorithmic FP32 flops of the per-seed solve kernels per executed unit.
 # Counted from the kernel's arithmetic (add/mul = 1, fma = 2, each
 # transcendental sin / cos / atan2 / sqrt / log / div = 1); see the design doc.
 # ---------------------------------------------------------------------------
@@ -389,6 +389,12 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    # the tiny configuration (8 targets x 64 seeds): the latency of one small solve
+    tb = W.config_tiny(host_seeds=False)
+    mt = measure(H, ctx, torch, tb, 50, 5)
+    line["tiny"] = {"workload": "tiny_panda_8x64", "ms_per_solve": mt["ms_per_step"], "latency_ms": mt["latency_ms"],
+                    "solved_targets": mt["solved_targets"], "stage_ms": mt["stage_ms"]}
+    log(f"tiny: {line['tiny']}")
     if not args.no_uneven:
         line["uneven"] = uneven(H, ctx, torch, 5, log)
     if args.large:

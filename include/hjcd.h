@@ -123,10 +123,11 @@ typedef struct {
 } hjcd_params;
 
 /* Per-call measurements of the last hjcd_solve / stage call made with
- * collect_stats = 1 on a context. */
+ * collect_stats = 1 on a context.  Stage times are HIP-event intervals on the
+ * call's stream: hjcd_solve reports its PO-CCD kernels in ms_cd and its PJ-IK
+ * kernels in ms_polish (with resampling, the replication in ms_resample). */
 typedef struct {
     float ms_init, ms_cd, ms_resample, ms_polish, ms_collide, ms_select;
-    float ms_solve_kernel;   /* fused CD + PJ-IK kernel(s) */
     float ms_total;          /* first to last event of the call */
     uint64_t seeds;          /* seeds processed */
     uint64_t cd_iters;       /* PO-CCD iterations executed (over all seeds) */
@@ -166,7 +167,7 @@ hjcd_status hjcd_load_scene(hjcd_ctx ctx, int32_t n_spheres, const float* sphere
 void hjcd_scene_destroy(hjcd_scene scene);
 
 /* ---- stages (one robot) ----------------------------------------------------
- * Each stage runs the same device code the fused solve runs. */
+ * Each stage runs the same device code the whole solve runs. */
 
 /* Forward kinematics (eq. fk) and geometric Jacobian (eq. jacobian) of S
  * configurations q [n][S]: pose [7][S] (px py pz qw qx qy qz, qw >= 0) and,

@@ -211,7 +211,7 @@ void group_targets(int32_t n_robots, int32_t T, const int32_t* robot_of_target, 
 namespace {
 
 // ---- stats ------------------------------------------------------------------
-enum StatStage { SS_INIT = 0, SS_CD, SS_RESAMPLE, SS_POLISH, SS_COLLIDE, SS_SELECT, SS_SOLVE };
+enum StatStage { SS_INIT = 0, SS_CD, SS_RESAMPLE, SS_POLISH, SS_COLLIDE, SS_SELECT };
 
 struct StatScope {
     hjcd_ctx c;
@@ -1010,7 +1010,6 @@ hjcd_status hjcd_get_stats(hjcd_ctx c, hjcd_stats* out) {
                 case SS_POLISH: c->stats.ms_polish += ms; break;
                 case SS_COLLIDE: c->stats.ms_collide += ms; break;
                 case SS_SELECT: c->stats.ms_select += ms; break;
-                case SS_SOLVE: c->stats.ms_solve_kernel += ms; break;
                 default: break;
             }
         }

@@ -72,7 +72,7 @@ class hjcd_params(C.Structure):
 class hjcd_stats(C.Structure):
     _fields_ = [("ms_init", C.c_float), ("ms_cd", C.c_float), ("ms_resample", C.c_float),
                 ("ms_polish", C.c_float), ("ms_collide", C.c_float), ("ms_select", C.c_float),
-                ("ms_solve_kernel", C.c_float), ("ms_total", C.c_float),
+                ("ms_total", C.c_float),
                 ("seeds", C.c_uint64), ("cd_iters", C.c_uint64), ("cd_perturb", C.c_uint64),
                 ("pol_iters", C.c_uint64), ("pol_trials", C.c_uint64), ("pol_dogleg", C.c_uint64),
                 ("pol_single", C.c_uint64), ("pol_perturb", C.c_uint64),
