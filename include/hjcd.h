@@ -300,8 +300,9 @@ typedef enum { HJCD_SERVE_BATCHED = 0, HJCD_SERVE_PLAIN = 1 } hjcd_serve_mode;
 typedef struct {
     int32_t mode;          /* hjcd_serve_mode */
     int64_t max_slots;     /* resident seed slots (rounded up to 64); 0 = from hbm_budget */
-    size_t hbm_budget;     /* bytes for resident state when max_slots = 0 (0 = a quarter of free
-                              memory, at most 8 GiB) */
+    size_t hbm_budget;     /* bytes for resident state when max_slots = 0, rounded down to whole
+                              64-slot blocks; HJCD_E_NOMEM below one block (0 = a quarter of
+                              free memory, at most 8 GiB) */
     int32_t max_targets;   /* resident targets (0 = slots / 32, between 64 and 2^20) */
     int32_t chunk_iters;   /* iterations per chunk (>= 1) */
     int32_t max_queue;     /* pending requests accepted before submit returns HJCD_E_BUSY */

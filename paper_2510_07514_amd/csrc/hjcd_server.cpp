@@ -540,9 +540,10 @@ hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene,
             HIP_TRY(hipMemGetInfo(&fr, &tot));
             budget = std::min<size_t>(fr / 4, (size_t)8 << 30);
         }
-        C = (int64_t)(budget / per_slot);
+        C = (int64_t)(budget / per_slot) / 64 * 64;  // the budget is a cap: whole blocks within it
+    } else {
+        C = ((C + 63) / 64) * 64;
     }
-    C = ((C + 63) / 64) * 64;
     if (C < 64) return fail(HJCD_E_NOMEM, "memory budget holds less than one 64-slot block");
     auto* srv = new hjcd_server_s();
     srv->ctx = ctx;

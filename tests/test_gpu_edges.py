@@ -153,3 +153,35 @@ def test_handles_outlive_their_context(H):
     sc.close()
     x = torch.ones(1000, device="cuda")
     assert float(x.sum().item()) == 1000.0
+
+
+def test_bitwise_repeatable(H, ctx):
+    """The same batch solved twice in one context, and once more in a fresh
+    context on another stream, gives bit-identical outputs: no result depends
+    on wave scheduling, atomics order or leftover device state."""
+    import torch
+    say("case: bitwise repeatability, 64 targets x 1024 seeds")
+    b = W.config_batched(T=64, M=1024)
+    rob = b.robots[0]
+    tg = O.targets_from_qstar(rob, b.q_star)
+    runs = [_solve(H, ctx, rob, b.scene, tg, b.seed_offsets, b.params) for _ in range(2)]
+    c2 = H.hjcd_ctx_create(0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        k, n, T = b.params["top_k"], rob.dof, b.T
+        o = [torch.zeros(T * k, n, device="cuda"), torch.zeros(T * k, device="cuda"), torch.zeros(T * k, device="cuda"),
+             torch.zeros(T * k, dtype=torch.uint8, device="cuda"), torch.zeros(T, dtype=torch.int32, device="cuda"),
+             torch.zeros(T, dtype=torch.uint8, device="cuda")]
+        rb = H.hjcd_load_robot(c2, rob)
+        sc = H.hjcd_load_scene(c2, b.scene.spheres, b.scene.boxes)
+        targets = torch.as_tensor(np.ascontiguousarray(np.asarray(tg, np.float32).T)).cuda()
+        H.hjcd_solve(c2, [rb], sc, targets, b.seed_offsets, H.params_from_dict(b.params), *o, stream=s)
+    s.synchronize()
+    runs.append(dict(zip(("q", "ep", "eo", "fl", "nf", "sv"), [x.cpu().numpy() for x in o])))
+    rb.close()
+    sc.close()
+    c2.close()
+    say(f"  solved {int(runs[0]['sv'].sum())} of {T}")
+    for r in runs[1:]:
+        for key in ("q", "ep", "eo", "fl", "nf", "sv"):
+            assert np.array_equal(runs[0][key], r[key]), key

@@ -228,6 +228,15 @@ def test_server_rejects_bad_requests(H, ctx):
         H.hjcd_server_create(ctx, rb, sc, H.params_from_dict(dict(s["params"], polish_iters=0)))
     with pytest.raises(H.HJCDError):
         H.hjcd_server_create(ctx, rb, sc, params, chunk_iters=0)
+    # a memory budget is a cap: the pool is the whole 64-slot blocks within
+    # it, and a budget below one block is refused
+    per_slot = 4 * (rob.dof + 3) + 9
+    with pytest.raises(H.HJCDError) as e:
+        H.hjcd_server_create(ctx, rb, sc, params, hbm_budget=per_slot * 63)
+    assert e.value.status == H.HJCD_E_NOMEM
+    srv = H.hjcd_server_create(ctx, rb, sc, params, hbm_budget=per_slot * 200)
+    assert H.hjcd_server_get_stats(srv)["max_slots"] == 192
+    srv.close()
 
 
 def test_serving_stream_latency_accounting(H, ctx):
