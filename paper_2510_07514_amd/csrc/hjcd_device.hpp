@@ -24,6 +24,15 @@ namespace hjcd {
 struct V3 {
     float x, y, z;
 };
+// Robot tables are read-only in every kernel.  PJ-IK reads them through the
+// constant address space: loads at uniform addresses (every joint constant)
+// then go to the scalar unit, into SGPRs, instead of through the vector memory
+// path into one VGPR per lane.  That matters where a kernel runs one wave per
+// SIMD (20 joints: nothing else hides the vector-load latency of each FK
+// step); PO-CCD keeps the generic pointer (measured faster there).
+using RobotRef = const __attribute__((address_space(4))) DevRobot*;
+__device__ __forceinline__ RobotRef robot_ref(const DevRobot* p) { return (RobotRef)p; }
+
 __device__ __forceinline__ V3 mk(float x, float y, float z) { return V3{x, y, z}; }
 __device__ __forceinline__ V3 operator+(V3 a, V3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ __forceinline__ V3 operator-(V3 a, V3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
@@ -99,8 +108,8 @@ __device__ __forceinline__ void sincos_cw(float x, float* sn, float* cs) {
 //   standard DH: joint i = frame i-1; p += a (R Rz(theta)).X + d R.Z;
 //                R <- R Rz(theta) Rx(alpha)
 // ----------------------------------------------------------------------------
-template <int NM, bool STORE>
-__device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n, const float* th,
+template <int NM, bool STORE, typename RB>
+__device__ __forceinline__ void fk_chain(RB rb, int n, const float* th,
                                          V3* P, V3* Z, Frame& ee) {
     Frame T = identity_frame();
     if (rb->conv == 0) {
@@ -147,7 +156,7 @@ __device__ __forceinline__ void fk_chain(const DevRobot* __restrict__ rb, int n,
         }
     }
     // end effector = T_0n * tool
-    const float* tl = rb->tool;
+    const auto* tl = rb->tool;
     ee.p = axpy(tl[11], T.Z, axpy(tl[7], T.Y, axpy(tl[3], T.X, T.p)));
     if (rb->tool_rot) {
         ee.X = axpy(tl[8], T.Z, axpy(tl[4], T.Y, tl[0] * T.X));
@@ -315,8 +324,8 @@ __device__ __forceinline__ U4 draw(uint64_t seed, uint32_t m, uint32_t tkey, uin
 // theta <- clip(theta + mu + sigma z), z ~ N(0, I) by Box-Muller: joint j takes
 // word pair (2p, 2p+1), p = (j % 4) / 2, of block j / 4; cos for even j, sin
 // for odd j.
-template <int NM>
-__device__ __forceinline__ void perturb(const DevRobot* __restrict__ rb, int n, float* th,
+template <int NM, typename RB>
+__device__ __forceinline__ void perturb(RB rb, int n, float* th,
                                         uint64_t seed, uint32_t m, uint32_t tkey, uint32_t stage,
                                         uint32_t iter, float mu, float sigma) {
 #pragma unroll
@@ -714,7 +723,7 @@ __device__ __forceinline__ void jcol(const V3* Jp, const V3* Z, int j, float* c)
 }
 
 template <int NM>
-__device__ __forceinline__ float trial_cost(const DevRobot* __restrict__ rb, int n, const Target& tg,
+__device__ __forceinline__ float trial_cost(RobotRef rb, int n, const Target& tg,
                                             const float* tt) {
     Frame ee;
     V3 Pd[1], Zd[1];
@@ -754,7 +763,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int r) {
 }
 
 template <int NM>
-__device__ __forceinline__ void line_search_spread(const DevRobot* __restrict__ rb, int n, const Target& tg,
+__device__ __forceinline__ void line_search_spread(RobotRef rb, int n, const Target& tg,
                                                    const KParams& kp, float* th, const float* dth, float* tt,
                                                    float c0, bool& done, Counters& cnt) {
     // alpha = 1 on the searching lanes
@@ -834,7 +843,7 @@ __device__ __forceinline__ void line_search_spread(const DevRobot* __restrict__ 
 // push-through form dtheta = D^-1 J^T W (W J D^-1 J^T W + lam I)^-1 W e.
 // ----------------------------------------------------------------------------
 template <int NM, bool SPREAD = true>
-__device__ __forceinline__ void pj_ik(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
+__device__ __forceinline__ void pj_ik(RobotRef rb, int n, const Target& tg, const KParams& kp,
                                       uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
                                       Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
                                       int k1, Err& out_err) {

@@ -69,7 +69,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     }
     if (do_polish) {
         bool frozen = !live;
-        pj_ik<NM, SPREAD>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
+        pj_ik<NM, SPREAD>(robot_ref(a.rb), n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
                   0, a.kp.polish_iters, e);
     }
     if (!do_cd && !do_polish && a.targets) {
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
         if (frozen) st |= SLOT_CD_FROZEN;
     } else {
         bool frozen = !live || (st & SLOT_POL_FROZEN);
-        pj_ik<NM, SolveOcc<NM, 0>::spread>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0,
+        pj_ik<NM, SolveOcc<NM, 0>::spread>(robot_ref(a.rb), n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0,
                                           blk.k1, er);
         // the exit test of iteration k1 (or the one after the last iteration)
         // on the state this chunk leaves: a seed converged by the chunk's last
