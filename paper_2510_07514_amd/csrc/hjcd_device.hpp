@@ -837,22 +837,21 @@ __device__ __forceinline__ void line_search_spread(RobotRef rb, int n, const Tar
 }
 
 // ----------------------------------------------------------------------------
-// PJ-IK (Alg. PJ-IK, Sec. IV-B) on one seed.  SPREAD selects the spread
-// line search above (same results; fewer passes, more live registers).
+// One PJ-IK iteration (Alg. PJ-IK, Sec. IV-B), number `it`, on one seed per
+// lane.  SPREAD selects the spread line search above (same results; fewer
+// passes, more live registers).
 // LM step: (J^T W^2 J + lam D) dtheta = J^T W^2 e is solved in its 6 x 6
 // push-through form dtheta = D^-1 J^T W (W J D^-1 J^T W + lam I)^-1 W e.
 // ----------------------------------------------------------------------------
 template <int NM, bool SPREAD = true>
-__device__ __forceinline__ void pj_ik(RobotRef rb, int n, const Target& tg, const KParams& kp,
-                                      uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
-                                      Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
-                                      int k1, Err& out_err) {
-    float last_ep = 0.f, last_phi = 0.f;
+__device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg, const KParams& kp,
+                                           uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
+                                           Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int it,
+                                           float& last_ep, float& last_phi) {
     V3 Jp[NM], Z[NM];
     float dth[NM], tt[NM];
     const float R = kp.trust_R;
-    for (int it = k0; it < k1; ++it) {
-        if (wave_all(frozen) && !traj) break;
+    {
         bool done = true;  // lane needs no further fallback this iteration
         float c0 = 0.f;
         float e6[6], w6[6];
@@ -1161,6 +1160,21 @@ __device__ __forceinline__ void pj_ik(RobotRef rb, int n, const Target& tg, cons
             ++cnt.pol_perturb;
         }
     }
+}
+
+// Iterations [k0, k1) of PJ-IK on one seed per lane; out_err is the residual
+// at the configuration the last iteration produced (when want_err).
+template <int NM, bool SPREAD = true>
+__device__ __forceinline__ void pj_ik(RobotRef rb, int n, const Target& tg, const KParams& kp,
+                                      uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
+                                      Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
+                                      int k1, Err& out_err, bool want_err = true) {
+    float last_ep = 0.f, last_phi = 0.f;
+    for (int it = k0; it < k1; ++it) {
+        if (wave_all(frozen) && !traj) break;
+        pj_ik_iter<NM, SPREAD>(rb, n, tg, kp, m, tkey, th, live, frozen, cnt, traj, S, s, it, last_ep, last_phi);
+    }
+    if (!want_err) return;  // the caller continues this seed in a later call
     Frame ee;
     V3 Pd[1], Zd[1];
     fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);

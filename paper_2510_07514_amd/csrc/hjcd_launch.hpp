@@ -56,7 +56,16 @@ struct SolveArgs {
     unsigned long long* counters;  // [9] or nullptr
     int32_t variant;         // occupancy variant (0 default, 1: >= 2 waves per SIMD)
     int32_t block_threads;   // workgroup size: 64, 128 or 256 (0 = 256)
+    int64_t seeds_per_wave;  // PJ-IK seed streaming: seeds per wave (set by the launch)
 };
+
+// Seeds per lane of a PJ-IK launch over Sv seeds: Sv / (8192 x 64) between 1
+// and 8, so a launch keeps at least about 8,192 waves (several per wave slot
+// of the chip); above 1 the launch streams seeds through its waves.
+inline int64_t stream_factor(int64_t Sv) {
+    const int64_t r = Sv / (64 * 8192);
+    return r < 1 ? 1 : (r > 8 ? 8 : r);
+}
 
 hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
 

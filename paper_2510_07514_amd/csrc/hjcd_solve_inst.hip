@@ -90,6 +90,88 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     flush_counters(cnt, a.counters, a.counters != nullptr);
 }
 
+// PJ-IK with seed streaming.  Wave w owns the seeds [w P, (w + 1) P) of the
+// launch (P = seeds_per_wave, a multiple of 64) and starts on the first 64;
+// a lane whose seed has converged or run all its iterations writes that
+// seed's result and takes the wave's next seed.  Lanes stay busy while the
+// range lasts instead of idling once their seed has converged.  A seed's
+// iterations, keys and arithmetic do not depend on its lane or on when it
+// starts, so the results equal those of one seed per lane.
+template <int NM, bool SPREAD>
+__device__ __forceinline__ void polish_stream(const SolveArgs& a) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t P = a.seeds_per_wave;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    int64_t next = w * P;
+    const int64_t end = next + P < a.map.Sv ? next + P : a.map.Sv;
+    const int n = kExactN ? HJCD_NM : a.n;
+    const RobotRef rb = robot_ref(a.rb);
+    const int K = a.kp.polish_iters;
+    Counters cnt;
+    Slot sl;
+    sl.s = 0;
+    sl.t = 0;
+    sl.m = 0;
+    sl.tkey = 0;
+    Target tg{};
+    float th[NM];
+#pragma unroll
+    for (int j = 0; j < NM; ++j) th[j] = 0.f;
+    bool has = false, frozen = true;
+    int it = 0;
+    float last_ep = 0.f, last_phi = 0.f;
+    for (;;) {
+        // free lanes take the wave's next seeds, in lane order
+        const uint64_t fr = __ballot(!has);
+        if (next < end && fr != 0ull) {
+            const int64_t v = next + __popcll(fr & ((1ull << lane) - 1ull));
+            if (!has && v < end) {
+                sl = map_lane(a.map, v);
+                if (a.targets) tg = load_target(a.targets, a.map.T, sl.t);
+                if (a.init_mode == INIT_UNIFORM) {
+                    uniform_seed<NM>(a.rb, n, th, a.kp.seed, sl.m, sl.tkey);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j)
+                        if (j < n) th[j] = clampf(a.q_in[(int64_t)j * a.q_in_stride + sl.s], a.rb->lo[j], a.rb->hi[j]);
+                }
+                has = true;
+                frozen = false;
+                it = 0;
+            }
+            next += __popcll(fr);
+        }
+        if (!wave_any(has)) break;
+        const bool run = has && !frozen && it < K;
+        if (wave_any(run)) {
+            bool fz = !run;
+            pj_ik_iter<NM, SPREAD>(rb, n, tg, a.kp, sl.m, sl.tkey, th, false, fz, cnt, nullptr, a.S, sl.s, it,
+                                   last_ep, last_phi);
+            if (run) {
+                frozen = fz;
+                ++it;
+            }
+        }
+        // converged, or all iterations run: the seed's result
+        if (has && (frozen || it >= K)) {
+            Frame ee;
+            V3 Pd[1], Zd[1];
+            fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
+            const Err e = residual(ee, tg);
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) a.q_out[(int64_t)j * a.S + sl.s] = th[j];
+            for (int j = n; j < a.n_rows; ++j) a.q_out[(int64_t)j * a.S + sl.s] = 0.f;
+            if (a.err_p) a.err_p[sl.s] = sqrtf(e.ep2);
+            if (a.err_o) a.err_o[sl.s] = e.phi;
+            if (a.cost) a.cost[sl.s] = cost_of(e);
+            has = false;
+            frozen = true;
+        }
+    }
+    flush_counters(cnt, a.counters, a.counters != nullptr);
+}
+
 // Both stages as the arguments say (the stage entry points, resampling).
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
@@ -108,6 +190,13 @@ template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish(
     SolveArgs a) {
     solve_body<NM, SolveOcc<NM, V>::spread>(a, false, true);
+}
+
+// PJ-IK only, streaming seeds through the waves (large launches).
+template <int NM, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish_stream(
+    SolveArgs a) {
+    polish_stream<NM, SolveOcc<NM, V>::spread>(a);
 }
 
 // ----------------------------------------------------------------------------
@@ -186,8 +275,22 @@ hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
     const bool cd_only = a.do_cd && !a.do_polish && !a.traj;
     const bool pol_only = !a.do_cd && a.do_polish && !a.traj;
+    // PJ-IK streams seeds through its waves once the launch holds enough
+    // seeds to keep every wave slot busy with several seeds per lane, in the
+    // buckets that run one or two waves per SIMD (measured: with three waves
+    // per SIMD the other waves already fill the issue slots an idle lane
+    // leaves, and streaming only lengthens the tail)
+    const int64_t sf = HJCD_NM > 16 ? stream_factor(a.map.Sv) : 1;
+    SolveArgs ps = a;
+    ps.seeds_per_wave = 64 * sf;
+    const int64_t seeds_per_block = ps.seeds_per_wave * (bt / 64);
+    const unsigned nbp = (unsigned)((a.map.Sv + seeds_per_block - 1) / seeds_per_block);
     if (cd_only)
         hipLaunchKernelGGL((k_cd<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
+    else if (pol_only && sf > 1 && a.variant == 1)
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1>), dim3(nbp), dim3(bt), 0, st, ps);
+    else if (pol_only && sf > 1)
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0>), dim3(nbp), dim3(bt), 0, st, ps);
     else if (pol_only && a.variant == 1)
         hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
     else if (pol_only)

@@ -488,8 +488,22 @@ def test_large_full_size_sampled(H, ctx):
     sv = o["sv"].cpu().numpy()[tsel]
     nf = o["nf"].cpu().numpy()[tsel]
     say(f"  gpu: solved {int(o['sv'].sum().item())}/{T}; sample solved {sv.tolist()} n_free {nf.tolist()}")
-    tg = O.targets_from_qstar(rob, [b.q_star[t] for t in tsel]).astype(np.float64)
+    # The full launch streams seeds through its PJ-IK waves (25.6 M seeds);
+    # the sampled targets solved alone (2,048 seeds, one seed per lane) with
+    # the same target keys give bit-identical results.
     M = int(b.seed_offsets[1] - b.seed_offsets[0])
+    sub = {kk: torch.zeros((8 * k, n) if kk == "q" else (8 * k if kk in ("ep", "eo", "fl") else 8),
+                           dtype=v.dtype, device="cuda") for kk, v in o.items()}
+    keys = torch.as_tensor(tsel.astype(np.int32)).cuda()
+    H.hjcd_solve(ctx, [rb], sc, pose[:, torch.as_tensor(tsel).cuda()].contiguous(), np.arange(9, dtype=np.int64) * M,
+                 p, sub["q"], sub["ep"], sub["eo"], sub["fl"], sub["nf"], sub["sv"], target_keys=keys)
+    _sync()
+    assert np.array_equal(sub["q"].cpu().numpy().reshape(8, k, n), q)
+    assert np.array_equal(sub["ep"].cpu().numpy().reshape(8, k), ep)
+    assert np.array_equal(sub["eo"].cpu().numpy().reshape(8, k), eo)
+    assert np.array_equal(sub["fl"].cpu().numpy().reshape(8, k), fl)
+    assert np.array_equal(sub["nf"].cpu().numpy(), nf) and np.array_equal(sub["sv"].cpu().numpy(), sv)
+    tg = O.targets_from_qstar(rob, [b.q_star[t] for t in tsel]).astype(np.float64)
     ref = O.solve(rob, b.scene, tg, np.arange(9, dtype=np.int64) * M, b.params, seeds=None,
                   target_keys=tsel.astype(np.uint32), nthreads=0)
     say(f"  oracle: sample solved {ref['solved'].tolist()} n_free {ref['n_free'].tolist()}")
