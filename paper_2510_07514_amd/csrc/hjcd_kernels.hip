@@ -98,6 +98,47 @@ __device__ __forceinline__ float box_d2(V3 c, const float* __restrict__ b) {
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v);
 __device__ __forceinline__ uint64_t cost_key(float c, uint32_t m);
 
+constexpr int kObsGroup = 4;  // obstacles whose loads are issued together
+
+// One environment sphere (centre co, radius ro) against link spheres f0 ..
+// f0 + fc - 1 of the link with frame F, for the lanes whose coarse test `ch`
+// hit; counts the coarse test of every lane not yet colliding.  Returns true
+// when every lane of the wave collides (the caller stops).
+__device__ __forceinline__ bool sphere_obstacle(const DevRobot* __restrict__ rb, const Frame& F, int f0, int fc,
+                                                V3 co, float ro, bool ch, bool& hit, uint32_t& n_coarse,
+                                                uint32_t& n_fine) {
+    n_coarse += hit ? 0u : 1u;
+    if (!wave_any(ch)) return false;
+    for (int k = 0; k < fc; ++k) {
+        const float* sp = rb->sph[f0 + k];
+        if (ch && !hit) {
+            const V3 c = xform(F, sp[0], sp[1], sp[2]);
+            const V3 df = c - co;
+            const float r2 = sp[3] + ro;
+            ++n_fine;
+            if (dot(df, df) < r2 * r2) hit = true;
+        }
+    }
+    return wave_all(hit);
+}
+
+// One environment box (centre b[0..2], half extents b[4..6]) against the
+// link spheres, for the lanes whose coarse test `ch` hit.
+__device__ __forceinline__ void box_obstacle(const DevRobot* __restrict__ rb, const Frame& F, int f0, int fc,
+                                             const float* __restrict__ b, bool ch, bool& hit, uint32_t& n_coarse,
+                                             uint32_t& n_fine) {
+    n_coarse += hit ? 0u : 1u;
+    if (!wave_any(ch)) return;
+    for (int k = 0; k < fc; ++k) {
+        const float* sp = rb->sph[f0 + k];
+        if (ch && !hit) {
+            const V3 c = xform(F, sp[0], sp[1], sp[2]);
+            ++n_fine;
+            if (box_d2(c, b) < sp[3] * sp[3]) hit = true;
+        }
+    }
+}
+
 // Collision test of one lane whose joint values are q[i * q_stride + s];
 // inactive lanes count as done so the wave can leave early.  Returns the
 // collision flag of an active lane.
@@ -121,42 +162,56 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
         if (Rc < 0.f) continue;
         const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
         const int f0 = rb->link_first[l], fc = rb->link_count[l];
-        for (int o = 0; o < n_osph; ++o) {
+        // Obstacles in groups of kObsGroup: the group's (uniform) loads and
+        // coarse distances first, so the loads of a group are in flight
+        // together, then the tests in obstacle order exactly as one at a time
+        // (same flags, counters and early exits).
+        bool stop = false;
+        int o = 0;
+        for (; o + kObsGroup <= n_osph && !stop; o += kObsGroup) {
+            V3 co[kObsGroup];
+            float ro[kObsGroup], d2[kObsGroup];
+#pragma unroll
+            for (int i = 0; i < kObsGroup; ++i) {
+                const float* q4 = os + 4 * (o + i);
+                co[i] = mk(q4[0], q4[1], q4[2]);
+                ro[i] = q4[3];
+                const V3 d = cc - co[i];
+                d2[i] = dot(d, d);
+            }
+#pragma unroll
+            for (int i = 0; i < kObsGroup; ++i) {
+                const float rr = Rc + ro[i];
+                if (sphere_obstacle(rb, F, f0, fc, co[i], ro[i], !hit && d2[i] < rr * rr, hit, n_coarse, n_fine)) {
+                    stop = true;
+                    break;
+                }
+            }
+        }
+        for (; o < n_osph && !stop; ++o) {
             const V3 co = mk(os[4 * o], os[4 * o + 1], os[4 * o + 2]);
             const float ro = os[4 * o + 3];
             const V3 d = cc - co;
             const float rr = Rc + ro;
-            const bool ch = !hit && dot(d, d) < rr * rr;
-            n_coarse += hit ? 0u : 1u;
-            if (wave_any(ch)) {
-                for (int k = 0; k < fc; ++k) {
-                    const float* sp = rb->sph[f0 + k];
-                    if (ch && !hit) {
-                        const V3 c = xform(F, sp[0], sp[1], sp[2]);
-                        const V3 df = c - co;
-                        const float r2 = sp[3] + ro;
-                        ++n_fine;
-                        if (dot(df, df) < r2 * r2) hit = true;
-                    }
+            stop = sphere_obstacle(rb, F, f0, fc, co, ro, !hit && dot(d, d) < rr * rr, hit, n_coarse, n_fine);
+        }
+        o = 0;
+        stop = wave_all(hit);
+        for (; o + kObsGroup <= n_obox && !stop; o += kObsGroup) {
+            float bd2[kObsGroup];
+#pragma unroll
+            for (int i = 0; i < kObsGroup; ++i) bd2[i] = box_d2(cc, ob + 8 * (o + i));
+#pragma unroll
+            for (int i = 0; i < kObsGroup; ++i) {
+                if (wave_all(hit)) {
+                    stop = true;
+                    break;
                 }
-                if (wave_all(hit)) break;
+                box_obstacle(rb, F, f0, fc, ob + 8 * (o + i), !hit && bd2[i] < Rc * Rc, hit, n_coarse, n_fine);
             }
         }
-        for (int o = 0; o < n_obox && !wave_all(hit); ++o) {
-            const float* b = ob + 8 * o;
-            const bool ch = !hit && box_d2(cc, b) < Rc * Rc;
-            n_coarse += hit ? 0u : 1u;
-            if (wave_any(ch)) {
-                for (int k = 0; k < fc; ++k) {
-                    const float* sp = rb->sph[f0 + k];
-                    if (ch && !hit) {
-                        const V3 c = xform(F, sp[0], sp[1], sp[2]);
-                        ++n_fine;
-                        if (box_d2(c, b) < sp[3] * sp[3]) hit = true;
-                    }
-                }
-            }
-        }
+        for (; o < n_obox && !wave_all(hit); ++o)
+            box_obstacle(rb, F, f0, fc, ob + 8 * o, !hit && box_d2(cc, ob + 8 * o) < Rc * Rc, hit, n_coarse, n_fine);
     }
     // self collision on the allowed link pairs
     for (int pi = 0; pi < rb->n_pairs && !wave_all(hit); ++pi) {
