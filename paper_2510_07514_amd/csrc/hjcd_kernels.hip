@@ -98,7 +98,7 @@ __device__ __forceinline__ float box_d2(V3 c, const float* __restrict__ b) {
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v);
 __device__ __forceinline__ uint64_t cost_key(float c, uint32_t m);
 
-constexpr int kObsGroup = 4;  // obstacles whose loads are issued together
+constexpr int kObsGroup = 8;  // obstacles whose loads are issued together (measured: 1, 2, 4, 8)
 
 // One environment sphere (centre co, radius ro) against link spheres f0 ..
 // f0 + fc - 1 of the link with frame F, for the lanes whose coarse test `ch`
