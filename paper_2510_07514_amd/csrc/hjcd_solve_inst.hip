@@ -172,6 +172,17 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
     flush_counters(cnt, a.counters, a.counters != nullptr);
 }
 
+// Occupancy of the PJ-IK-only kernels: in the 20-joint bucket two waves per
+// SIMD by default (one PJ-IK iteration per call keeps the kernel at 256
+// registers with about 60 spilled; measured 31% faster than one wave on the
+// 20-joint workload), one as the alternative; elsewhere as SolveOcc (at 24
+// and 32 joints two waves would spill 150-400 registers).
+template <int NM, int V>
+struct PolishOcc {
+    static constexpr int waves = (NM > 16 && NM <= 20) ? (V == 0 ? 2 : 1) : SolveOcc<NM, V>::waves;
+    static constexpr bool spread = SolveOcc<NM, V>::spread;
+};
+
 // Both stages as the arguments say (the stage entry points, resampling).
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
@@ -187,16 +198,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
 }
 
 template <int NM, int V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish(
     SolveArgs a) {
-    solve_body<NM, SolveOcc<NM, V>::spread>(a, false, true);
+    solve_body<NM, PolishOcc<NM, V>::spread>(a, false, true);
 }
 
 // PJ-IK only, streaming seeds through the waves (large launches).
 template <int NM, int V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_polish_stream(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish_stream(
     SolveArgs a) {
-    polish_stream<NM, SolveOcc<NM, V>::spread>(a);
+    polish_stream<NM, PolishOcc<NM, V>::spread>(a);
 }
 
 // ----------------------------------------------------------------------------
