@@ -172,15 +172,21 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
     flush_counters(cnt, a.counters, a.counters != nullptr);
 }
 
-// Occupancy of the PJ-IK-only kernels: in the 20-joint bucket two waves per
-// SIMD by default (one PJ-IK iteration per call keeps the kernel at 256
-// registers with about 60 spilled; measured 31% faster than one wave on the
-// 20-joint workload), one as the alternative; elsewhere as SolveOcc (at 24
-// and 32 joints two waves would spill 150-400 registers).
+// Occupancy of the single-stage kernels.  In the 20-joint bucket two waves per
+// SIMD, although the kernels then spill (PJ-IK about 60 registers, PO-CCD
+// about 210): at one wave per SIMD nothing hides the latency of a wave's own
+// dependent instructions, and two waves measured faster (PJ-IK 104 -> 71 ms,
+// PO-CCD 76 -> 49 ms on 20,000 x 256).  PJ-IK keeps one wave as the
+// alternative variant.  Elsewhere as SolveOcc (not measured at 24 and 32
+// joints, where two waves would spill 150-400 registers in PJ-IK).
 template <int NM, int V>
 struct PolishOcc {
     static constexpr int waves = (NM > 16 && NM <= 20) ? (V == 0 ? 2 : 1) : SolveOcc<NM, V>::waves;
     static constexpr bool spread = SolveOcc<NM, V>::spread;
+};
+template <int NM>
+struct CdOcc {
+    static constexpr int waves = (NM > 16 && NM <= 20) ? 2 : SolveOcc<NM, 0>::waves;
 };
 
 // Both stages as the arguments say (the stage entry points, resampling).
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
 // PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
 // kernel compiled for its stage alone.
 template <int NM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, 0>::waves))) void k_cd(SolveArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::waves))) void k_cd(SolveArgs a) {
     solve_body<NM, false>(a, true, false);
 }
 
