@@ -326,6 +326,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the 8 x 64 latency case (profiling runs)")
     ap.add_argument("--large", action="store_true", help="also time the 100,000 x 256 random 20-joint workload")
     ap.add_argument("--serve-rates", default="2000,10000,50000")
     ap.add_argument("--serve-duration", type=float, default=1.0, help="seconds of each request stream")
@@ -390,11 +391,13 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     # the tiny configuration (8 targets x 64 seeds): the latency of one small solve
-    tb = W.config_tiny(host_seeds=False)
-    mt = measure(H, ctx, torch, tb, 50, 5)
-    line["tiny"] = {"workload": "tiny_panda_8x64", "ms_per_solve": mt["ms_per_step"], "latency_ms": mt["latency_ms"],
-                    "solved_targets": mt["solved_targets"], "stage_ms": mt["stage_ms"]}
-    log(f"tiny: {line['tiny']}")
+    if not args.no_tiny:
+        tb = W.config_tiny(host_seeds=False)
+        mt = measure(H, ctx, torch, tb, 50, 5)
+        line["tiny"] = {"workload": "tiny_panda_8x64", "ms_per_solve": mt["ms_per_step"],
+                        "latency_ms": mt["latency_ms"], "solved_targets": mt["solved_targets"],
+                        "stage_ms": mt["stage_ms"]}
+        log(f"tiny: {line['tiny']}")
     if not args.no_uneven:
         line["uneven"] = uneven(H, ctx, torch, 5, log)
     if args.large:
