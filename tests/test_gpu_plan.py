@@ -125,3 +125,39 @@ def test_plan_rejects_resampling(H, ctx):
     with pytest.raises(H.HJCDError) as e:
         H.hjcd_plan_create(ctx, rbs, sc, targets, b.seed_offsets, p, *outs, robot_of_target=b.robot_of_target)
     assert e.value.status == H.HJCD_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("tune", [False, True])
+def test_plan_streaming_launch_equals_eager(H, ctx, tune):
+    """A 20-joint batch large enough for the PJ-IK launch to stream seeds
+    through its waves (4,200 x 256 seeds): a plan replay, autotuned or not,
+    gives bit-identical results to the eager hjcd_solve."""
+    import torch
+    say(f"case: streaming PJ-IK in a plan, tune={tune}")
+    b = W.config_large(T=4200)
+    assert int(b.seed_offsets[-1]) >= 2 * 8192 * 64
+    rbs, sc, targets = _setup(H, ctx, b)
+    k, n_max = b.params["top_k"], b.n_max
+    p = H.params_from_dict(b.params)
+    ref = _outs(b.T, k, n_max)
+    H.hjcd_solve(ctx, rbs, sc, targets, b.seed_offsets, p, *ref, robot_of_target=b.robot_of_target)
+    ref = _host(ref)
+    outs = _outs(b.T, k, n_max)
+    plan = H.hjcd_plan_create(ctx, rbs, sc, targets, b.seed_offsets, p, *outs, robot_of_target=b.robot_of_target,
+                              tune=tune)
+    ch = H.hjcd_plan_choice(plan, 0)
+    say(f"  choice {ch}")
+    for rep in range(2):
+        for o in outs:
+            o.zero_()
+        H.hjcd_plan_execute(plan)
+        got = _host(outs)
+        if ch["variant"] == 0:  # the eager solve's kernels, another launch shape at most
+            for nm, g, e in zip(("q", "err_p", "err_o", "flag", "n_free", "solved"), got, ref):
+                assert np.array_equal(g, e), (rep, nm)
+        else:  # as in test_plan_replays_equal_eager_solve
+            assert np.sum(got[5] != ref[5]) <= 1
+            assert np.abs(got[4] - ref[4]).max() <= 2
+            assert np.all(np.abs(got[0] - ref[0]) <= 1e-4, axis=1).mean() >= 0.95
+    say(f"  solved {int(ref[5].sum())} of {b.T}")
+    plan.close()
