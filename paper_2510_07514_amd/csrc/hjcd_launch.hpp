@@ -54,7 +54,7 @@ struct SolveArgs {
     int32_t do_cd, do_polish;
     KernelParams kp;
     unsigned long long* counters;  // [9] or nullptr
-    int32_t variant;         // occupancy variant (0 default, 1: >= 2 waves per SIMD)
+    int32_t variant;         // occupancy variant of PJ-IK (0 default, 1 the alternative)
     int32_t block_threads;   // workgroup size: 64, 128 or 256 (0 = 256)
     int64_t seeds_per_wave;  // PJ-IK seed streaming: seeds per wave (set by the launch)
 };
