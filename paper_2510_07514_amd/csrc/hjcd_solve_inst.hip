@@ -34,6 +34,34 @@ struct SolveOcc {
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
+// Initial joint values of seed sl: uniform draws in the limits, or the
+// caller's values (live lanes) clamped to the limits.
+template <int NM>
+__device__ __forceinline__ void init_seed(const SolveArgs& a, int n, const Slot& sl, bool live, float* th) {
+#pragma unroll
+    for (int j = 0; j < NM; ++j) th[j] = 0.f;
+    if (a.init_mode == INIT_UNIFORM) {
+        uniform_seed<NM>(a.rb, n, th, a.kp.seed, sl.m, sl.tkey);
+    } else if (live) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j)
+            if (j < n) th[j] = clampf(a.q_in[(int64_t)j * a.q_in_stride + sl.s], a.rb->lo[j], a.rb->hi[j]);
+    }
+}
+
+// Result of the seed in slot s: joint values (rows n .. n_rows - 1 zero for
+// mixed-dof batches), |r_p|, phi and cost.
+template <int NM>
+__device__ __forceinline__ void write_seed(const SolveArgs& a, int n, const float* th, const Err& e, int64_t s) {
+#pragma unroll
+    for (int j = 0; j < NM; ++j)
+        if (j < n) a.q_out[(int64_t)j * a.S + s] = th[j];
+    for (int j = n; j < a.n_rows; ++j) a.q_out[(int64_t)j * a.S + s] = 0.f;
+    if (a.err_p) a.err_p[s] = sqrtf(e.ep2);
+    if (a.err_o) a.err_o[s] = e.phi;
+    if (a.cost) a.cost[s] = cost_of(e);
+}
+
 template <int NM, bool SPREAD>
 __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool do_polish) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -51,15 +79,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     Target tg{};
     if (a.targets) tg = load_target(a.targets, a.map.T, sl.t);
     float th[NM];
-#pragma unroll
-    for (int j = 0; j < NM; ++j) th[j] = 0.f;
-    if (a.init_mode == INIT_UNIFORM) {
-        uniform_seed<NM>(a.rb, n, th, a.kp.seed, sl.m, sl.tkey);
-    } else if (live) {
-#pragma unroll
-        for (int j = 0; j < NM; ++j)
-            if (j < n) th[j] = clampf(a.q_in[(int64_t)j * a.q_in_stride + sl.s], a.rb->lo[j], a.rb->hi[j]);
-    }
+    init_seed<NM>(a, n, sl, live, th);
     Counters cnt;
     Err e{};
     if (do_cd) {
@@ -69,8 +89,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     }
     if (do_polish) {
         bool frozen = !live;
-        pj_ik<NM, SPREAD>(robot_ref(a.rb), n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, do_cd ? nullptr : a.traj, a.S, sl.s,
-                  0, a.kp.polish_iters, e);
+        pj_ik<NM, SPREAD>(robot_ref(a.rb), n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt,
+                          do_cd ? nullptr : a.traj, a.S, sl.s, 0, a.kp.polish_iters, e);
     }
     if (!do_cd && !do_polish && a.targets) {
         Frame ee;
@@ -78,15 +98,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
         fk_chain<NM, false>(a.rb, n, th, Pd, Zd, ee);
         e = residual(ee, tg);
     }
-    if (live) {
-#pragma unroll
-        for (int j = 0; j < NM; ++j)
-            if (j < n) a.q_out[(int64_t)j * a.S + sl.s] = th[j];
-        for (int j = n; j < a.n_rows; ++j) a.q_out[(int64_t)j * a.S + sl.s] = 0.f;
-        if (a.err_p) a.err_p[sl.s] = sqrtf(e.ep2);
-        if (a.err_o) a.err_o[sl.s] = e.phi;
-        if (a.cost) a.cost[sl.s] = cost_of(e);
-    }
+    if (live) write_seed<NM>(a, n, th, e, sl.s);
     flush_counters(cnt, a.counters, a.counters != nullptr);
 }
 
@@ -128,13 +140,7 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
             if (!has && v < end) {
                 sl = map_lane(a.map, v);
                 if (a.targets) tg = load_target(a.targets, a.map.T, sl.t);
-                if (a.init_mode == INIT_UNIFORM) {
-                    uniform_seed<NM>(a.rb, n, th, a.kp.seed, sl.m, sl.tkey);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < NM; ++j)
-                        if (j < n) th[j] = clampf(a.q_in[(int64_t)j * a.q_in_stride + sl.s], a.rb->lo[j], a.rb->hi[j]);
-                }
+                init_seed<NM>(a, n, sl, true, th);
                 has = true;
                 frozen = false;
                 it = 0;
@@ -157,14 +163,7 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
             Frame ee;
             V3 Pd[1], Zd[1];
             fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
-            const Err e = residual(ee, tg);
-#pragma unroll
-            for (int j = 0; j < NM; ++j)
-                if (j < n) a.q_out[(int64_t)j * a.S + sl.s] = th[j];
-            for (int j = n; j < a.n_rows; ++j) a.q_out[(int64_t)j * a.S + sl.s] = 0.f;
-            if (a.err_p) a.err_p[sl.s] = sqrtf(e.ep2);
-            if (a.err_o) a.err_o[sl.s] = e.phi;
-            if (a.cost) a.cost[sl.s] = cost_of(e);
+            write_seed<NM>(a, n, th, residual(ee, tg), sl.s);
             has = false;
             frozen = true;
         }
