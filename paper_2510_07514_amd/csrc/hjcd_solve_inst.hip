@@ -171,21 +171,22 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
     flush_counters(cnt, a.counters, a.counters != nullptr);
 }
 
-// Occupancy of the single-stage kernels.  In the 20-joint bucket two waves per
-// SIMD, although the kernels then spill (PJ-IK about 60 registers, PO-CCD
-// about 210): at one wave per SIMD nothing hides the latency of a wave's own
-// dependent instructions, and two waves measured faster (PJ-IK 104 -> 71 ms,
-// PO-CCD 76 -> 49 ms on 20,000 x 256).  PJ-IK keeps one wave as the
-// alternative variant.  Elsewhere as SolveOcc (not measured at 24 and 32
-// joints, where two waves would spill 150-400 registers in PJ-IK).
+// Occupancy of the single-stage kernels.  In the 20- and 24-joint buckets two
+// waves per SIMD, although the kernels then spill (at 20 joints PJ-IK about 60
+// registers, PO-CCD about 210): at one wave per SIMD nothing hides the latency
+// of a wave's own dependent instructions, and two waves measured faster (20
+// joints, 20,000 x 256: PJ-IK 104 -> 71 ms, PO-CCD 76 -> 49 ms; 24 joints,
+// 8,000 x 256: PO-CCD 37.3 -> 34.1 ms, PJ-IK 34.8 -> 34.3 ms).  At 32 joints
+// the spills outweigh it (PO-CCD 49 -> 62 ms, PJ-IK 33 -> 38 ms): one wave.
+// PJ-IK keeps the other occupancy as the alternative variant.
 template <int NM, int V>
 struct PolishOcc {
-    static constexpr int waves = (NM > 16 && NM <= 20) ? (V == 0 ? 2 : 1) : SolveOcc<NM, V>::waves;
+    static constexpr int waves = (NM > 16 && NM <= 24) ? (V == 0 ? 2 : 1) : SolveOcc<NM, V>::waves;
     static constexpr bool spread = SolveOcc<NM, V>::spread;
 };
 template <int NM>
 struct CdOcc {
-    static constexpr int waves = (NM > 16 && NM <= 20) ? 2 : SolveOcc<NM, 0>::waves;
+    static constexpr int waves = (NM > 16 && NM <= 24) ? 2 : SolveOcc<NM, 0>::waves;
 };
 
 // Both stages as the arguments say (the stage entry points, resampling).
