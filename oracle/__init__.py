@@ -22,6 +22,10 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 ST_INIT, ST_CD, ST_RESAMPLE, ST_POLISH = 0, 1, 2, 3
 
+# operation-count categories (hjcd_oracle.h, OR_OPS_*)
+OPS_CATEGORIES = ("misc", "eval", "init", "cd_iter", "cd_perturb", "pj_iter", "pj_trial", "pj_dogleg",
+                  "pj_single", "pj_perturb", "resample", "collide", "select", "instr")
+
 
 def build() -> str:
     """Compile the oracle with g++ (plain IEEE double, no FMA contraction)."""
@@ -62,7 +66,8 @@ class _Params(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("iters_run", C.c_int32), ("frozen_at", C.c_int32), ("n_perturb", C.c_int32),
-                ("n_trials", C.c_int32), ("n_dogleg", C.c_int32), ("n_single", C.c_int32)]
+                ("n_trials", C.c_int32), ("n_dogleg", C.c_int32), ("n_single", C.c_int32),
+                ("n_tie_pick", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,6 +102,11 @@ def lib():
                                     dp, dp, ip]
         L.or_collide.argtypes = [C.POINTER(_Robot), C.POINTER(_Scene), dp, ip, dp]
         L.or_select.argtypes = [C.c_int32, ip, dp, C.c_int32, ip]
+        L.or_resample.argtypes = [C.POINTER(_Robot), C.c_int32, C.POINTER(C.c_int64), dp, dp, up,
+                                  C.POINTER(_Params), dp]
+        L.or_ops_reset.argtypes = []
+        L.or_ops_reset.restype = None
+        L.or_ops_get.argtypes = [C.c_int32, C.POINTER(C.c_uint64)]
         L.or_solve.argtypes = [C.POINTER(_Robot), C.POINTER(_Scene), C.c_int32, dp,
                                C.POINTER(C.c_int64), dp, up, C.POINTER(_Params),
                                dp, dp, dp, dp, ip, dp, dp, dp, ip, ip, ip, C.c_int32]
@@ -308,6 +318,48 @@ def select(flag, cost, k):
     o = np.zeros(k, np.int32)
     lib().or_select(int(fl.shape[0]), _ptr(fl, C.c_int32), _ptr(c), k, _ptr(o, C.c_int32))
     return o
+
+
+def resample(robot, offsets, q_in, cost_in, p, target_keys=None):
+    """Top-K ranking and floor(B/K) noisy copies per target (Alg. HJCD-IK):
+    q_in [S, n], cost_in [S] -> q_out [T * B', n], B' = floor(B/K) K."""
+    rh = _rh(robot)
+    n = rh.n
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    T = offs.shape[0] - 1
+    K, B = int(p["resample_K"]), int(p["resample_B"])
+    Bp = (B // K) * K if K > 0 else 0
+    q = _d(np.asarray(q_in, np.float64).reshape(-1))
+    c = _d(cost_in)
+    tk = None if target_keys is None else np.ascontiguousarray(target_keys, dtype=np.uint32)
+    out = np.zeros((T * Bp, n))
+    pr = params(p)
+    rc = lib().or_resample(C.byref(rh.c), T, _ptr(offs, C.c_int64), _ptr(q), _ptr(c), _ptr(tk, C.c_uint32),
+                           C.byref(pr), _ptr(out))
+    if rc != 0:
+        raise ValueError("or_resample rejected its input")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# operation counts
+# ---------------------------------------------------------------------------
+
+def ops_reset():
+    lib().or_ops_reset()
+
+
+def ops_get():
+    """{category: dict(add, mul, div, sqrt, trans, units, flops)} with flops =
+    add + mul + div + sqrt (transcendental calls counted apart)."""
+    out = {}
+    buf = (C.c_uint64 * 6)()
+    for i, name in enumerate(OPS_CATEGORIES):
+        lib().or_ops_get(i, buf)
+        d = dict(zip(("add", "mul", "div", "sqrt", "trans", "units"), [int(x) for x in buf]))
+        d["flops"] = d["add"] + d["mul"] + d["div"] + d["sqrt"]
+        out[name] = d
+    return out
 
 
 # ---------------------------------------------------------------------------

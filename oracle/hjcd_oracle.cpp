@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -20,7 +21,57 @@ const double kPi = 3.14159265358979323846;
 const double kInf = std::numeric_limits<double>::infinity();
 
 // ---------------------------------------------------------------------------
-// 4x4 homogeneous transforms, 3-vectors
+// Operation counts (instrumentation; they never change a result).  Every
+// helper below adds the floating-point operations its own body executes to
+// the counter of the unit of work being executed: add (add, subtract), mul,
+// div, sqrt, and transcendental calls (sin, cos, atan2, acos, log, pow).
+// Comparisons, min / max, sign flips and copies are not counted.
+// ---------------------------------------------------------------------------
+struct Ops {
+    uint64_t add, mul, div, sqrt, trans, units;
+};
+thread_local Ops tl_ops[OR_OPS_NCAT];
+thread_local int tl_cat = OR_OPS_EVAL;
+std::mutex g_ops_mu;
+Ops g_ops[OR_OPS_NCAT];
+
+inline void ops(uint64_t add, uint64_t mul, uint64_t div = 0, uint64_t sq = 0, uint64_t tr = 0) {
+    Ops& o = tl_ops[tl_cat];
+    o.add += add;
+    o.mul += mul;
+    o.div += div;
+    o.sqrt += sq;
+    o.trans += tr;
+}
+
+// The operations executed while a Unit is alive go to category c, which
+// counts one unit more.
+struct Unit {
+    int prev;
+    explicit Unit(int c) : prev(tl_cat) {
+        tl_cat = c;
+        tl_ops[c].units++;
+    }
+    ~Unit() { tl_cat = prev; }
+};
+
+// Moves this thread's counts into the process totals.
+void flush_ops() {
+    std::lock_guard<std::mutex> lk(g_ops_mu);
+    for (int c = 0; c < OR_OPS_NCAT; ++c) {
+        Ops& t = tl_ops[c];
+        g_ops[c].add += t.add;
+        g_ops[c].mul += t.mul;
+        g_ops[c].div += t.div;
+        g_ops[c].sqrt += t.sqrt;
+        g_ops[c].trans += t.trans;
+        g_ops[c].units += t.units;
+        t = Ops{0, 0, 0, 0, 0, 0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rigid transforms (4x4 homogeneous, last row 0 0 0 1), 3-vectors
 // ---------------------------------------------------------------------------
 struct H4 {
     double m[4][4];
@@ -33,53 +84,47 @@ H4 eye4() {
     return t;
 }
 
+// a b for rigid a, b: rotation rows times rotation columns, translation
+// R_a p_b + p_a (the bottom row stays 0 0 0 1).
 H4 mul(const H4& a, const H4& b) {
-    H4 c;
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) {
-            double s = 0.0;
-            for (int k = 0; k < 4; ++k) s += a.m[i][k] * b.m[k][j];
-            c.m[i][j] = s;
-        }
+    H4 c = eye4();
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) c.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+        c.m[i][3] = a.m[i][3] + a.m[i][0] * b.m[0][3] + a.m[i][1] * b.m[1][3] + a.m[i][2] * b.m[2][3];
+    }
+    ops(27, 36);
     return c;
-}
-
-H4 rot_x(double t) {
-    H4 r = eye4();
-    r.m[1][1] = std::cos(t);
-    r.m[1][2] = -std::sin(t);
-    r.m[2][1] = std::sin(t);
-    r.m[2][2] = std::cos(t);
-    return r;
-}
-
-H4 rot_z(double t) {
-    H4 r = eye4();
-    r.m[0][0] = std::cos(t);
-    r.m[0][1] = -std::sin(t);
-    r.m[1][0] = std::sin(t);
-    r.m[1][1] = std::cos(t);
-    return r;
-}
-
-H4 trans(double x, double y, double z) {
-    H4 r = eye4();
-    r.m[0][3] = x;
-    r.m[1][3] = y;
-    r.m[2][3] = z;
-    return r;
 }
 
 struct V3 {
     double x, y, z;
 };
 V3 v3(double x, double y, double z) { return V3{x, y, z}; }
-V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
-V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
-V3 operator*(double s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
-double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-V3 cross(V3 a, V3 b) { return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
-double norm(V3 a) { return std::sqrt(dot(a, a)); }
+V3 operator+(V3 a, V3 b) {
+    ops(3, 0);
+    return v3(a.x + b.x, a.y + b.y, a.z + b.z);
+}
+V3 operator-(V3 a, V3 b) {
+    ops(3, 0);
+    return v3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+V3 operator*(double s, V3 a) {
+    ops(0, 3);
+    return v3(s * a.x, s * a.y, s * a.z);
+}
+V3 neg(V3 a) { return v3(-a.x, -a.y, -a.z); }
+double dot(V3 a, V3 b) {
+    ops(2, 3);
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+V3 cross(V3 a, V3 b) {
+    ops(3, 6);
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+double norm(V3 a) {
+    ops(0, 0, 0, 1);
+    return std::sqrt(dot(a, a));
+}
 
 // Quaternion (w, x, y, z), Hamilton convention.
 struct Q4 {
@@ -88,9 +133,10 @@ struct Q4 {
 };
 Q4 qmul(Q4 a, Q4 b) {
     // (a0, a)(b0, b) = (a0 b0 - a.b, a0 b + b0 a + a x b)
+    ops(1, 1);
     return Q4{a.w * b.w - dot(a.v, b.v), a.w * b.v + b.w * a.v + cross(a.v, b.v)};
 }
-Q4 qconj(Q4 a) { return Q4{a.w, -1.0 * a.v}; }
+Q4 qconj(Q4 a) { return Q4{a.w, neg(a.v)}; }
 
 // Shepperd (1978): pick the largest of trace, R00, R11, R22 for the division.
 Q4 quat_from_R(const double R[3][3]) {
@@ -100,20 +146,24 @@ Q4 quat_from_R(const double R[3][3]) {
         double s = 2.0 * std::sqrt(1.0 + tr);
         q.w = 0.25 * s;
         q.v = v3((R[2][1] - R[1][2]) / s, (R[0][2] - R[2][0]) / s, (R[1][0] - R[0][1]) / s);
+        ops(2 + 1 + 3, 2, 3, 1);
     } else if (R[0][0] >= R[1][1] && R[0][0] >= R[2][2]) {
         double s = 2.0 * std::sqrt(1.0 + R[0][0] - R[1][1] - R[2][2]);
         q.w = (R[2][1] - R[1][2]) / s;
         q.v = v3(0.25 * s, (R[0][1] + R[1][0]) / s, (R[0][2] + R[2][0]) / s);
+        ops(2 + 3 + 3, 2, 3, 1);
     } else if (R[1][1] >= R[2][2]) {
         double s = 2.0 * std::sqrt(1.0 - R[0][0] + R[1][1] - R[2][2]);
         q.w = (R[0][2] - R[2][0]) / s;
         q.v = v3((R[0][1] + R[1][0]) / s, 0.25 * s, (R[1][2] + R[2][1]) / s);
+        ops(2 + 3 + 3, 2, 3, 1);
     } else {
         double s = 2.0 * std::sqrt(1.0 - R[0][0] - R[1][1] + R[2][2]);
         q.w = (R[1][0] - R[0][1]) / s;
         q.v = v3((R[0][2] + R[2][0]) / s, (R[1][2] + R[2][1]) / s, 0.25 * s);
+        ops(2 + 3 + 3, 2, 3, 1);
     }
-    if (q.w < 0.0) q = Q4{-q.w, -1.0 * q.v};
+    if (q.w < 0.0) q = Q4{-q.w, neg(q.v)};
     return q;
 }
 
@@ -123,6 +173,7 @@ Q4 quat_from_R(const double R[3][3]) {
 struct Robot {
     int n = 0, conv = 0;
     double a[OR_MAX_DOF], d[OR_MAX_DOF], alpha[OR_MAX_DOF], off[OR_MAX_DOF];
+    double ca[OR_MAX_DOF], sa[OR_MAX_DOF];  // cos / sin of alpha (constants of the chain)
     double lo[OR_MAX_DOF], hi[OR_MAX_DOF];
     H4 tool;
     std::vector<int> sph_link;
@@ -139,6 +190,8 @@ bool load_robot(const or_robot* in, Robot& r) {
         r.a[i] = in->a[i];
         r.d[i] = in->d[i];
         r.alpha[i] = in->alpha[i];
+        r.ca[i] = std::cos(r.alpha[i]);
+        r.sa[i] = std::sin(r.alpha[i]);
         r.off[i] = in->offset[i];
         r.lo[i] = in->q_min[i];
         r.hi[i] = in->q_max[i];
@@ -169,22 +222,61 @@ V3 col(const H4& t, int c) { return v3(t.m[0][c], t.m[1][c], t.m[2][c]); }
 // Modified DH (Craig): {i-1}T_i = Rx(alpha_i) Tx(a_i) Rz(theta_i + o_i) Tz(d_i);
 // joint i turns about z of frame i.  Standard DH:
 // {i-1}T_i = Rz(theta_i + o_i) Tz(d_i) Tx(a_i) Rx(alpha_i); joint i turns about
-// z of frame i-1.  End effector = T_0n * tool.
+// z of frame i-1.  Each link transform is the product of those four
+// elementary motions written out (c = cos, s = sin, t = theta + offset):
+//   modified: R = [[ct, -st, 0], [ca st, ca ct, -sa], [sa st, sa ct, ca]],
+//             p = (a, -sa d, ca d)
+//   standard: R = [[ct, -st ca, st sa], [st, ct ca, -ct sa], [0, sa, ca]],
+//             p = (a ct, a st, d)
+// End effector = T_0n * tool.
+H4 dh_link(const Robot& r, int i, double theta) {
+    const double t = theta + r.off[i];
+    const double ct = std::cos(t), st = std::sin(t);
+    const double ca = r.ca[i], sa = r.sa[i];
+    ops(1, 6, 0, 0, 2);
+    H4 L = eye4();
+    if (r.conv == 0) {
+        L.m[0][0] = ct;
+        L.m[0][1] = -st;
+        L.m[0][2] = 0.0;
+        L.m[1][0] = ca * st;
+        L.m[1][1] = ca * ct;
+        L.m[1][2] = -sa;
+        L.m[2][0] = sa * st;
+        L.m[2][1] = sa * ct;
+        L.m[2][2] = ca;
+        L.m[0][3] = r.a[i];
+        L.m[1][3] = -sa * r.d[i];
+        L.m[2][3] = ca * r.d[i];
+    } else {
+        L.m[0][0] = ct;
+        L.m[0][1] = -st * ca;
+        L.m[0][2] = st * sa;
+        L.m[1][0] = st;
+        L.m[1][1] = ct * ca;
+        L.m[1][2] = -ct * sa;
+        L.m[2][0] = 0.0;
+        L.m[2][1] = sa;
+        L.m[2][2] = ca;
+        L.m[0][3] = r.a[i] * ct;
+        L.m[1][3] = r.a[i] * st;
+        L.m[2][3] = r.d[i];
+    }
+    return L;
+}
+
 void fk(const Robot& r, const double* th, FK& o) {
     H4 T = eye4();
     o.link[0] = T;
     for (int i = 0; i < r.n; ++i) {
-        double t = th[i] + r.off[i];
         if (r.conv == 0) {
-            H4 L = mul(mul(rot_x(r.alpha[i]), trans(r.a[i], 0, 0)), mul(rot_z(t), trans(0, 0, r.d[i])));
-            T = mul(T, L);
+            T = mul(T, dh_link(r, i, th[i]));
             o.P[i] = col(T, 3);
             o.z[i] = col(T, 2);
         } else {
             o.P[i] = col(T, 3);
             o.z[i] = col(T, 2);
-            H4 L = mul(mul(rot_z(t), trans(0, 0, r.d[i])), mul(trans(r.a[i], 0, 0), rot_x(r.alpha[i])));
-            T = mul(T, L);
+            T = mul(T, dh_link(r, i, th[i]));
         }
         o.link[i + 1] = T;
     }
@@ -232,6 +324,13 @@ struct Res {
     double ep, cost;
 };
 
+// Switches the category that operations are counted in (no unit counted).
+struct Scope {
+    int prev;
+    explicit Scope(int c) : prev(tl_cat) { tl_cat = c; }
+    ~Scope() { tl_cat = prev; }
+};
+
 // q_err = q_t (x) q_e^-1 is taken with w >= 0 so that the printed formula
 // 2 atan2(|v|, |w|) v/|v| points along the short rotation (reading of eq.
 // quat_diff); phi and a_hat of eq. (angle_axis) then follow from the same
@@ -241,19 +340,23 @@ Res residual(const Target& tg, const V3& p_ee, const double R[3][3]) {
     r.rp = tg.p - p_ee;
     Q4 qe = quat_from_R(R);
     Q4 qerr = qmul(tg.q, qconj(qe));
-    if (qerr.w < 0.0) qerr = Q4{-qerr.w, -1.0 * qerr.v};
+    if (qerr.w < 0.0) qerr = Q4{-qerr.w, neg(qerr.v)};
     double s = norm(qerr.v);
     r.phi = 2.0 * std::atan2(s, qerr.w);
+    ops(0, 1, 0, 0, 1);
     r.v = qerr.v;
     if (s > 1e-20) {
         r.omega = (r.phi / s) * qerr.v;
         r.ahat = (1.0 / s) * qerr.v;
+        ops(0, 0, 2);
     } else {
         r.omega = (2.0 / qerr.w) * qerr.v;
         r.ahat = v3(0, 0, 0);
+        ops(0, 0, 1);
     }
     r.ep = norm(r.rp);
     r.cost = 0.5 * (dot(r.rp, r.rp) + dot(r.omega, r.omega));
+    ops(1, 1);
     return r;
 }
 
@@ -295,7 +398,10 @@ enum { ST_INIT = 0, ST_CD = 1, ST_RESAMPLE = 2, ST_POLISH = 3 };
 
 // The top 24 bits of a word give a uniform in (0, 1) that is exact in both
 // single and double precision.
-double uni24(uint32_t x) { return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0); }
+double uni24(uint32_t x) {
+    ops(1, 1);
+    return ((double)(x >> 8) + 0.5) * (1.0 / 16777216.0);
+}
 
 void draw_block(uint64_t seed, uint32_t m, uint32_t tkey, uint32_t stage, uint32_t iter,
                 uint32_t block, uint32_t out[4]) {
@@ -315,6 +421,7 @@ void normals(uint64_t seed, uint32_t m, uint32_t tkey, uint32_t stage, uint32_t 
         double u1 = uni24(x[2 * p]), u2 = uni24(x[2 * p + 1]);
         double rad = std::sqrt(-2.0 * std::log(u1));
         z[j] = (j % 2 == 0) ? rad * std::cos(2.0 * kPi * u2) : rad * std::sin(2.0 * kPi * u2);
+        ops(0, 3, 0, 1, 2);
     }
 }
 
@@ -323,6 +430,7 @@ void uniform_seed(const Robot& rb, uint64_t seed, uint32_t m, uint32_t tkey, dou
         uint32_t x[4];
         draw_block(seed, m, tkey, ST_INIT, 0, (uint32_t)(j / 4), x);
         th[j] = rb.lo[j] + (rb.hi[j] - rb.lo[j]) * uni24(x[j % 4]);
+        ops(2, 1);
     }
 }
 
@@ -333,6 +441,7 @@ void perturb(const Robot& rb, const or_params& p, uint32_t m, uint32_t tkey, uin
     double z[OR_MAX_DOF];
     normals(p.rng_seed, m, tkey, stage, iter, rb.n, z);
     for (int j = 0; j < rb.n; ++j) th[j] = clip(th[j] + p.mu + p.sigma * z[j], rb.lo[j], rb.hi[j]);
+    ops(2 * rb.n, rb.n);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +486,7 @@ void cd_candidates(const Robot& rb, const Target& tg, const or_params& p, const 
     const int n = rb.n;
     // Annealed orientation factor delta(k) of eq. (ori_update).
     double delta = std::max(p.delta_min, p.delta0 * std::pow(p.delta_decay, (double)k));
+    ops(0, 1, 0, 0, 1);
     for (int j = 0; j < n; ++j) {
         // Position candidate: eq. (vec_proj) projects u = P_ee - P_j and
         // v = P_t - P_j onto the plane normal to the joint axis; the angle
@@ -395,17 +505,23 @@ void cd_candidates(const Robot& rb, const Target& tg, const or_params& p, const 
             double mag = std::acos(c);
             double sgn = dot(z, cross(uh, vh)) >= 0.0 ? 1.0 : -1.0;
             d = sgn * mag;
+            ops(0, 1, 2, 0, 1);
         }
         mg.add(std::fabs(du - p.proj_eps));
         mg.add(std::fabs(dv - p.proj_eps));
         dp[j] = clip(th[j] + d, rb.lo[j], rb.hi[j]) - th[j];
+        ops(2, 0);
 
         // Orientation candidate, eq. (ori_update): delta(k) sgn(a_hat . r_j) phi,
         // sgn(0) = 0.
         double az = dot(r.ahat, z);
         double sg = az > 0.0 ? 1.0 : (az < 0.0 ? -1.0 : 0.0);
         dor[j] = clip(th[j] + delta * sg * r.phi, rb.lo[j], rb.hi[j]) - th[j];
-        if (2.0 * delta * r.phi > harm) mg.add(std::fabs(dot(r.v, z)));
+        ops(2, 2);
+        if (2.0 * delta * r.phi > harm) {
+            Scope instr(OR_OPS_INSTR);
+            mg.add(std::fabs(dot(r.v, z)));
+        }
 
         // Scores: full FK at the moved configuration.
         double tt[OR_MAX_DOF];
@@ -416,6 +532,7 @@ void cd_candidates(const Robot& rb, const Target& tg, const or_params& p, const 
         tt[j] = th[j] + dor[j];
         Res ro_ = eval(rb, tg, tt);
         so[j] = dot(ro_.omega, ro_.omega);
+        ops(2, 0);
     }
 }
 
@@ -426,11 +543,15 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
             double* th, double* traj, double* margin, or_stage_stats& st, double harm) {
     const int n = rb.n;
     const int K = p.cd_sweeps;
-    st = or_stage_stats{0, -1, 0, 0, 0, 0};
+    st = or_stage_stats{0, -1, 0, 0, 0, 0, 0};
     for (int k = 0; k < K; ++k) {
         FK f;
-        fk(rb, th, f);
-        Res r = residual(tg, f.p_ee, f.R_ee);
+        Res r;
+        {
+            Unit u(OR_OPS_EVAL);
+            fk(rb, th, f);
+            r = residual(tg, f.p_ee, f.R_ee);
+        }
         write_row(traj, k, n, th, r);
         Margin mg;
 
@@ -447,26 +568,38 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
             return;
         }
 
+        Unit u(OR_OPS_CD_ITER);
         double dp[OR_MAX_DOF], dor[OR_MAX_DOF], sp[OR_MAX_DOF], so[OR_MAX_DOF];
         cd_candidates(rb, tg, p, th, k, f, r, dp, dor, sp, so, mg, harm);
 
         // Greedy picks: the lowest joint whose score (|r_p| for position, |omega|
         // for orientation) lies within tie_eps of the best one.
+        double ds[OR_MAX_DOF], os[OR_MAX_DOF];
         double dmin = kInf, omin = kInf;
+        int jp0 = 0, jo0 = 0;  // strict argmins (lowest index), for the tie statistic
         for (int j = 0; j < n; ++j) {
-            dmin = std::min(dmin, std::sqrt(sp[j]));
-            omin = std::min(omin, std::sqrt(so[j]));
+            ds[j] = std::sqrt(sp[j]);
+            os[j] = std::sqrt(so[j]);
+            if (ds[j] < dmin) {
+                dmin = ds[j];
+                jp0 = j;
+            }
+            if (os[j] < omin) {
+                omin = os[j];
+                jo0 = j;
+            }
         }
+        const double dlim = dmin + p.tie_eps, olim = omin + p.tie_eps;
+        ops(2, 0, 0, 2 * n);
         int jp = -1, jo = -1;
         for (int j = 0; j < n; ++j) {
-            if (jp < 0 && std::sqrt(sp[j]) <= dmin + p.tie_eps) jp = j;
-            if (jo < 0 && std::sqrt(so[j]) <= omin + p.tie_eps) jo = j;
+            if (jp < 0 && ds[j] <= dlim) jp = j;
+            if (jo < 0 && os[j] <= olim) jo = j;
         }
+        if (jp != jp0 || jo != jo0) st.n_tie_pick++;
         for (int j = 0; j < n; ++j) {
-            if (std::fabs(dp[jp]) + std::fabs(dp[j]) > harm)
-                mg.add(std::fabs(std::sqrt(sp[j]) - dmin - p.tie_eps));
-            if (std::fabs(dor[jo]) + std::fabs(dor[j]) > harm)
-                mg.add(std::fabs(std::sqrt(so[j]) - omin - p.tie_eps));
+            if (std::fabs(dp[jp]) + std::fabs(dp[j]) > harm) mg.add(std::fabs(ds[j] - dlim));
+            if (std::fabs(dor[jo]) + std::fabs(dor[j]) > harm) mg.add(std::fabs(os[j] - olim));
         }
 
         // theta_hat: both moves if they act on different joints, otherwise the
@@ -476,11 +609,13 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
         if (jp != jo) {
             hat[jp] += dp[jp];
             hat[jo] += dor[jo];
+            ops(2, 0);
         } else {
             if (std::fabs(dp[jp]) >= std::fabs(dor[jo]))
                 hat[jp] += dp[jp];
             else
                 hat[jo] += dor[jo];
+            ops(1, 0);
             if (std::fabs(dp[jp] - dor[jo]) > harm)
                 mg.add(std::fabs(std::fabs(dp[jp]) - std::fabs(dor[jo])));
         }
@@ -491,19 +626,25 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
         double e2p = dot(r.rp, r.rp), e2o = dot(r.omega, r.omega);
         double h2p = dot(rh.rp, rh.rp), h2o = dot(rh.omega, rh.omega);
         bool ia = (e2p - h2p) > p.gamma, ib = (e2o - h2o) > p.gamma;
+        ops(2, 0);
         double ma = std::fabs(e2p - h2p - p.gamma) / std::max(std::sqrt(e2p) + std::sqrt(h2p), 1e-30);
         double mb = std::fabs(e2o - h2o - p.gamma) / std::max(std::sqrt(e2o) + std::sqrt(h2o), 1e-30);
         mg.add(or_margin(ia, ma, ib, mb));
         if (ia || ib) {
             std::memcpy(th, hat, sizeof(double) * n);
         } else {
+            Unit up(OR_OPS_CD_PERTURB);
             perturb(rb, p, m, tkey, ST_CD, (uint32_t)k, th);
             st.n_perturb++;
         }
         st.iters_run++;
         if (margin) margin[k] = mg.v;
     }
-    Res r = eval(rb, tg, th);
+    Res r;
+    {
+        Unit u(OR_OPS_EVAL);
+        r = eval(rb, tg, th);
+    }
     write_row(traj, K, n, th, r);
     if (r.ep < p.eps_cd && r.phi < p.nu_cd) st.frozen_at = K;
 }
@@ -513,16 +654,23 @@ void po_ccd(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, u
 // ---------------------------------------------------------------------------
 // Solve A x = b for symmetric positive definite A (n x n, row-major) by Cholesky.
 bool chol_solve(int n, std::vector<double> A, const double* b, double* x) {
+    uint64_t fm = 0, fd = 0;  // multiply-subtract pairs, divisions
     for (int j = 0; j < n; ++j) {
         double s = A[j * n + j];
         for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
-        if (!(s > 0.0)) return false;
+        fm += j;
+        if (!(s > 0.0)) {
+            ops(fm, fm, fd, j + 1);
+            return false;
+        }
         double l = std::sqrt(s);
         A[j * n + j] = l;
         for (int i = j + 1; i < n; ++i) {
             double t = A[i * n + j];
             for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
             A[i * n + j] = t / l;
+            fm += j;
+            fd += 1;
         }
     }
     std::vector<double> y(n);
@@ -530,18 +678,24 @@ bool chol_solve(int n, std::vector<double> A, const double* b, double* x) {
         double t = b[i];
         for (int k = 0; k < i; ++k) t -= A[i * n + k] * y[k];
         y[i] = t / A[i * n + i];
+        fm += i;
+        fd += 1;
     }
     for (int i = n - 1; i >= 0; --i) {
         double t = y[i];
         for (int k = i + 1; k < n; ++k) t -= A[k * n + i] * x[k];
         x[i] = t / A[i * n + i];
+        fm += n - 1 - i;
+        fd += 1;
     }
+    ops(fm, fm, fd, n);
     return true;
 }
 
 double vnorm(int n, const double* x) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += x[i] * x[i];
+    double s = x[0] * x[0];
+    for (int i = 1; i < n; ++i) s += x[i] * x[i];
+    ops(n - 1, n, 0, 1);
     return std::sqrt(s);
 }
 
@@ -554,12 +708,14 @@ bool line_search(const Robot& rb, const Target& tg, const or_params& p, double* 
     const int n = rb.n;
     double alpha = 1.0;
     for (int i = 0; i <= p.ls_A; ++i) {
+        Unit u(OR_OPS_PJ_TRIAL);
         double tt[OR_MAX_DOF];
         double smax = 0.0;
         for (int j = 0; j < n; ++j) {
             tt[j] = clip(th[j] + alpha * step[j], rb.lo[j], rb.hi[j]);
             smax = std::max(smax, std::fabs(alpha * step[j]));
         }
+        ops(n, n);
         Res r = eval(rb, tg, tt);
         st.n_trials++;
         if (smax > harm) mg.add(std::fabs(std::sqrt(2.0 * r.cost) - std::sqrt(2.0 * c0)));
@@ -569,6 +725,7 @@ bool line_search(const Robot& rb, const Target& tg, const or_params& p, double* 
             return true;
         }
         alpha /= p.ls_beta;
+        ops(0, 0, 1);
     }
     return false;
 }
@@ -596,35 +753,51 @@ Lin linearise(const Robot& rb, const or_params& p, const FK& f, const Res& r) {
     for (int i = 0; i < 6; ++i) L.e[i] = e[i];
     // W normalises the rows of J (reading of Sec. IV-B).
     for (int i = 0; i < 6; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += L.J[i * n + j] * L.J[i * n + j];
-        L.w[i] = (p.weight_mode == 0) ? 1.0 / std::max(std::sqrt(s), 1e-6) : 1.0;
+        if (p.weight_mode != 0) {
+            L.w[i] = 1.0;
+            continue;
+        }
+        double s = L.J[i * n] * L.J[i * n];
+        for (int j = 1; j < n; ++j) s += L.J[i * n + j] * L.J[i * n + j];
+        L.w[i] = 1.0 / std::max(std::sqrt(s), 1e-6);
+        ops(n - 1, n, 1, 1);
     }
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < 6; ++i) s += L.J[i * n + j] * L.J[i * n + j];
+        double s = L.J[j] * L.J[j];
+        for (int i = 1; i < 6; ++i) s += L.J[i * n + j] * L.J[i * n + j];
         L.Dg[j] = s;
     }
+    ops(5 * n, 6 * n);
     return L;
 }
 
 // eq. (normal-eqs) read with W^T W on both sides and the sign that steps
 // toward the target: (J^T W^2 J + lambda D) dtheta = J^T W^2 e, solved as the
-// n x n system by Cholesky.  Unclipped.
+// n x n system by Cholesky (the matrix is symmetric: its lower triangle is
+// formed and mirrored).  Unclipped.
 void lm_step(const Lin& L, const or_params& p, double* dth) {
     const int n = L.n;
     std::vector<double> A(n * n, 0.0);
-    double b[OR_MAX_DOF];
+    double b[OR_MAX_DOF], w2[6], we[6];
+    for (int i = 0; i < 6; ++i) {
+        w2[i] = L.w[i] * L.w[i];
+        we[i] = w2[i] * L.e[i];
+    }
+    ops(0, 12);
     for (int a = 0; a < n; ++a) {
-        for (int c = 0; c < n; ++c) {
-            double s = 0.0;
-            for (int i = 0; i < 6; ++i) s += L.J[i * n + a] * L.w[i] * L.w[i] * L.J[i * n + c];
-            A[a * n + c] = s + (a == c ? p.lam * L.Dg[a] : 0.0);
+        for (int c = 0; c <= a; ++c) {
+            double s = L.J[a] * w2[0] * L.J[c];
+            for (int i = 1; i < 6; ++i) s += L.J[i * n + a] * w2[i] * L.J[i * n + c];
+            if (a == c) s += p.lam * L.Dg[a];
+            A[a * n + c] = s;
+            A[c * n + a] = s;
         }
-        double s = 0.0;
-        for (int i = 0; i < 6; ++i) s += L.J[i * n + a] * L.w[i] * L.w[i] * L.e[i];
+        double s = L.J[a] * we[0];
+        for (int i = 1; i < 6; ++i) s += L.J[i * n + a] * we[i];
         b[a] = s;
     }
+    const uint64_t pairs = (uint64_t)n * (n + 1) / 2;
+    ops(5 * pairs + n + 5 * n, 12 * pairs + n + 6 * n);
     chol_solve(n, A, b, dth);
 }
 
@@ -637,38 +810,47 @@ void dogleg_step(const Lin& L, const or_params& p, double* step, double* gd, dou
     const double R = p.trust_R;
     double g[OR_MAX_DOF];
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < 6; ++i) s += L.J[i * n + j] * L.e[i];
+        double s = L.J[j] * L.e[0];
+        for (int i = 1; i < 6; ++i) s += L.J[i * n + j] * L.e[i];
         g[j] = s;
     }
-    double gg = 0.0, jgjg = 0.0;
+    double Jg[6];
     for (int i = 0; i < 6; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += L.J[i * n + j] * g[j];
-        jgjg += s * s;  // |J g|^2
+        double s = L.J[i * n] * g[0];
+        for (int j = 1; j < n; ++j) s += L.J[i * n + j] * g[j];
+        Jg[i] = s;
     }
-    for (int j = 0; j < n; ++j) gg += g[j] * g[j];
+    double jgjg = Jg[0] * Jg[0];  // |J g|^2
+    for (int i = 1; i < 6; ++i) jgjg += Jg[i] * Jg[i];
+    double gg = g[0] * g[0];
+    for (int j = 1; j < n; ++j) gg += g[j] * g[j];
     double ac = jgjg > 0.0 ? gg / jgjg : 0.0;
     for (int j = 0; j < n; ++j) gd[j] = ac * g[j];
+    ops(5 * n + 6 * (n - 1) + 5 + (n - 1), 6 * n + 6 * n + 6 + n + n, 1);
     std::vector<double> JJt(36, 0.0);
     for (int a = 0; a < 6; ++a)
-        for (int c = 0; c < 6; ++c) {
-            double s = 0.0;
-            for (int j = 0; j < n; ++j) s += L.J[a * n + j] * L.J[c * n + j];
-            JJt[a * 6 + c] = s + (a == c ? p.lambda_gn : 0.0);
+        for (int c = 0; c <= a; ++c) {
+            double s = L.J[a * n] * L.J[c * n];
+            for (int j = 1; j < n; ++j) s += L.J[a * n + j] * L.J[c * n + j];
+            if (a == c) s += p.lambda_gn;
+            JJt[a * 6 + c] = s;
+            JJt[c * 6 + a] = s;
         }
+    ops(21 * (n - 1) + 6, 21 * n);
     double y[6];
     chol_solve(6, JJt, L.e, y);
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < 6; ++i) s += L.J[i * n + j] * y[i];
+        double s = L.J[j] * y[0];
+        for (int i = 1; i < 6; ++i) s += L.J[i * n + j] * y[i];
         gn[j] = s;
     }
+    ops(5 * n, 6 * n);
     double ngn = vnorm(n, gn), ngd = vnorm(n, gd);
     if (ngn <= R) {
         for (int j = 0; j < n; ++j) step[j] = gn[j];
     } else if (ngd >= R) {
         for (int j = 0; j < n; ++j) step[j] = R * gd[j] / ngd;
+        ops(0, n, n);
     } else {
         // |gn + tau d|^2 = R^2 is a convex quadratic, > 0 at tau = 0 and < 0 at
         // tau = 1: its smaller root, in the cancellation-free form.
@@ -682,6 +864,7 @@ void dogleg_step(const Lin& L, const or_params& p, double* step, double* gd, dou
         double den = -bb + std::sqrt(std::max(bb * bb - aa * cc, 0.0));
         double tau = den > 0.0 ? clip(cc / den, 0.0, 1.0) : 0.0;
         for (int j = 0; j < n; ++j) step[j] = gn[j] + tau * (gd[j] - gn[j]);
+        ops(3 * n + 3 + 2 * n, 2 * n + 4 + n, 1, 1);
     }
 }
 
@@ -690,20 +873,25 @@ void dogleg_step(const Lin& L, const or_params& p, double* step, double* gd, dou
 // coordinate-Newton length g^W_i* / (J^T W^2 J)_i*i*, clipped to [-R, R].
 int single_step(const Lin& L, const or_params& p, double* step, Margin& mg) {
     const int n = L.n;
-    double gw[OR_MAX_DOF];
+    double gw[OR_MAX_DOF], w2[6], we[6];
+    for (int i = 0; i < 6; ++i) {
+        w2[i] = L.w[i] * L.w[i];
+        we[i] = w2[i] * L.e[i];
+    }
     int is = 0;
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < 6; ++i) s += L.J[i * n + j] * L.w[i] * L.w[i] * L.e[i];
+        double s = L.J[j] * we[0];
+        for (int i = 1; i < 6; ++i) s += L.J[i * n + j] * we[i];
         gw[j] = s;
         if (std::fabs(gw[j]) > std::fabs(gw[is])) is = j;
     }
     for (int j = 0; j < n; ++j)
         if (j != is) mg.add(std::fabs(std::fabs(gw[is]) - std::fabs(gw[j])));
-    double h = 0.0;
-    for (int i = 0; i < 6; ++i) h += L.J[i * n + is] * L.w[i] * L.w[i] * L.J[i * n + is];
+    double h = L.J[is] * w2[0] * L.J[is];
+    for (int i = 1; i < 6; ++i) h += L.J[i * n + is] * w2[i] * L.J[i * n + is];
     for (int j = 0; j < n; ++j) step[j] = 0.0;
     step[is] = h > 0.0 ? clip(gw[is] / h, -p.trust_R, p.trust_R) : 0.0;
+    ops(5 * n + 5, 12 + 6 * n + 12, 1);
     return is;
 }
 
@@ -781,11 +969,15 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
     const int n = rb.n;
     const int K = p.polish_iters;
     const double R = p.trust_R;
-    st = or_stage_stats{0, -1, 0, 0, 0, 0};
+    st = or_stage_stats{0, -1, 0, 0, 0, 0, 0};
     for (int it = 0; it < K; ++it) {
         FK f;
-        fk(rb, th, f);
-        Res r = residual(tg, f.p_ee, f.R_ee);
+        Res r;
+        {
+            Unit u(OR_OPS_EVAL);
+            fk(rb, th, f);
+            r = residual(tg, f.p_ee, f.R_ee);
+        }
         write_row(traj, it, n, th, r);
         Margin mg;
         // Exit test of Alg. PJ-IK, evaluated on the configuration the previous
@@ -803,13 +995,16 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             return;
         }
         const double c0 = r.cost;
-        Lin L = linearise(rb, p, f, r);
-        if (p.shadow) L = perturbed(L, p, p.shadow * 1000003ull + (uint64_t)it);
-
-        // LM step, trust-region clamp, backtracking line search.
+        Lin L;
         double dth[OR_MAX_DOF];
-        lm_step(L, p, dth);
-        for (int j = 0; j < n; ++j) dth[j] = clip(dth[j], -R, R);
+        {
+            Unit u(OR_OPS_PJ_ITER);
+            L = linearise(rb, p, f, r);
+            if (p.shadow) L = perturbed(L, p, p.shadow * 1000003ull + (uint64_t)it);
+            // LM step, trust-region clamp, backtracking line search.
+            lm_step(L, p, dth);
+            for (int j = 0; j < n; ++j) dth[j] = clip(dth[j], -R, R);
+        }
         double alpha = 1.0;
         int kind = STEP_LM, is = 0;
         bool ok = line_search(rb, tg, p, th, dth, c0, mg, st, harm, &alpha);
@@ -819,12 +1014,17 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             alpha = 1.0;
             st.n_dogleg++;
             double step[OR_MAX_DOF], gd[OR_MAX_DOF], gn[OR_MAX_DOF];
-            dogleg_step(L, p, step, gd, gn);
+            {
+                Unit u(OR_OPS_PJ_DOGLEG);
+                dogleg_step(L, p, step, gd, gn);
+            }
+            Unit u(OR_OPS_PJ_TRIAL);
             double tt[OR_MAX_DOF], smax = 0.0;
             for (int j = 0; j < n; ++j) {
                 tt[j] = clip(th[j] + step[j], rb.lo[j], rb.hi[j]);
                 smax = std::max(smax, std::fabs(step[j]));
             }
+            ops(n, 0);
             Res rr = eval(rb, tg, tt);
             st.n_trials++;
             if (smax > harm) mg.add(std::fabs(std::sqrt(2.0 * rr.cost) - std::sqrt(2.0 * c0)));
@@ -838,19 +1038,30 @@ void pj_ik(const Robot& rb, const Target& tg, const or_params& p, uint32_t m, ui
             st.n_single++;
             double step[OR_MAX_DOF];
             kind = STEP_SINGLE;
-            is = single_step(L, p, step, mg);
+            {
+                Unit u(OR_OPS_PJ_SINGLE);
+                is = single_step(L, p, step, mg);
+            }
             ok = line_search(rb, tg, p, th, step, c0, mg, st, harm, &alpha);
         }
         if (!ok) {
+            Unit u(OR_OPS_PJ_PERTURB);
             kind = STEP_PERTURB;
             perturb(rb, p, m, tkey, ST_POLISH, (uint32_t)it, th);
             st.n_perturb++;
         }
-        if (sens) sens[it] = step_sensitivity(L, p, kind, alpha, is, it);
+        if (sens) {
+            Scope instr(OR_OPS_INSTR);
+            sens[it] = step_sensitivity(L, p, kind, alpha, is, it);
+        }
         st.iters_run++;
         if (margin) margin[it] = mg.v;
     }
-    Res r = eval(rb, tg, th);
+    Res r;
+    {
+        Unit u(OR_OPS_EVAL);
+        r = eval(rb, tg, th);
+    }
     write_row(traj, K, n, th, r);
     if (r.ep < p.eps_pol && r.phi < p.ups_pol) st.frozen_at = K;
 }
@@ -877,6 +1088,7 @@ void collide(const Robot& rb, const Scene& sc, const double* th, int& flag, doub
                   T.m[2][0] * q[0] + T.m[2][1] * q[1] + T.m[2][2] * q[2] + T.m[2][3]);
         rad[s] = q[3];
     }
+    ops(9 * ns, 9 * ns);
     flag = 0;
     mind = kInf;
     const int no = (int)sc.sph.size() / 4, nb = (int)sc.box.size() / 6;
@@ -886,6 +1098,8 @@ void collide(const Robot& rb, const Scene& sc, const double* th, int& flag, doub
             V3 dlt = c[s] - v3(ob[0], ob[1], ob[2]);
             double rr = rad[s] + ob[3];
             if (dot(dlt, dlt) < rr * rr) flag = 1;
+            ops(1, 1);
+            Scope instr(OR_OPS_INSTR);
             mind = std::min(mind, norm(dlt) - rr);
         }
         for (int o = 0; o < nb; ++o) {
@@ -897,6 +1111,7 @@ void collide(const Robot& rb, const Scene& sc, const double* th, int& flag, doub
                 q2 += ex * ex;
             }
             if (q2 < rad[s] * rad[s]) flag = 1;
+            ops(9, 4);
             mind = std::min(mind, std::sqrt(q2) - rad[s]);
         }
     }
@@ -907,6 +1122,8 @@ void collide(const Robot& rb, const Scene& sc, const double* th, int& flag, doub
                 V3 dlt = c[a] - c[b];
                 double rr = rad[a] + rad[b];
                 if (dot(dlt, dlt) < rr * rr) flag = 1;
+                ops(1, 1);
+                Scope instr(OR_OPS_INSTR);
                 mind = std::min(mind, norm(dlt) - rr);
             }
     }
@@ -1021,6 +1238,7 @@ int or_cd(const or_robot* rbi, const double* target, const or_params* pr, uint32
     Target tg = load_target(target);
     or_stage_stats s;
     po_ccd(rb, tg, *pr, seed_idx, target_key, theta, traj, margin, s, kHarm);
+    flush_ops();
     if (st) *st = s;
     return 0;
 }
@@ -1033,6 +1251,7 @@ int or_polish(const or_robot* rbi, const double* target, const or_params* pr, ui
     Target tg = load_target(target);
     or_stage_stats s;
     pj_ik(rb, tg, *pr, seed_idx, target_key, theta, traj, margin, sens, s, kHarm);
+    flush_ops();
     if (st) *st = s;
     return 0;
 }
@@ -1079,7 +1298,11 @@ int or_collide(const or_robot* rbi, const or_scene* sci, const double* theta, in
     }
     int f;
     double md;
-    collide(rb, sc, theta, f, md);
+    {
+        Unit u(OR_OPS_COLLIDE);
+        collide(rb, sc, theta, f, md);
+    }
+    flush_ops();
     if (flag) *flag = f;
     if (min_signed_dist) *min_signed_dist = md;
     return 0;
@@ -1091,6 +1314,50 @@ int or_select(int32_t m, const int32_t* flag, const double* cost, int32_t k, int
     return 0;
 }
 
+// Top-K ranking and noisy replication for one target (Alg. HJCD-IK): its M
+// seeds th [M*n] with costs cst [M] are ranked by (cost, index); copy i of
+// rank kk (i < floor(B/K), kk < K) is written to row i*K + kk of out
+// [floor(B/K)*K*n] as clip(theta + mu + sigma z), z drawn for seed index
+// i*K + kk at stage RESAMPLE.  A target with fewer than K seeds (M < K, M >= 1)
+// repeats its ranked seeds cyclically: rank kk takes the seed of rank kk mod M.
+void resample_target(const Robot& rb, const or_params& p, int M, const double* th, const double* cst,
+                     uint32_t tkey, double* out) {
+    const int n = rb.n;
+    const int K = p.resample_K;
+    const int copies = p.resample_B / K;
+    std::vector<int> idx(M);
+    for (int i = 0; i < M; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (cst[a] != cst[b]) return cst[a] < cst[b];
+        return a < b;
+    });
+    for (int i = 0; i < copies; ++i)
+        for (int kk = 0; kk < K; ++kk) {
+            Unit u(OR_OPS_RESAMPLE);
+            double* x = out + (size_t)(i * K + kk) * n;
+            std::memcpy(x, th + (size_t)idx[kk % M] * n, sizeof(double) * n);
+            perturb(rb, p, (uint32_t)(i * K + kk), tkey, ST_RESAMPLE, 0, x);
+        }
+}
+
+int or_resample(const or_robot* rbi, int32_t T, const int64_t* offsets, const double* q_in,
+                const double* cost_in, const uint32_t* target_keys, const or_params* pr, double* q_out) {
+    Robot rb;
+    if (!load_robot(rbi, rb) || !pr || T < 0 || pr->resample_K < 1 || pr->resample_B < pr->resample_K) return -1;
+    for (int t = 0; t < T; ++t)
+        if (offsets[t + 1] <= offsets[t]) return -1;
+    const int n = rb.n;
+    const int64_t Bp = (int64_t)(pr->resample_B / pr->resample_K) * pr->resample_K;
+    for (int t = 0; t < T; ++t) {
+        const int64_t b0 = offsets[t];
+        const int M = (int)(offsets[t + 1] - b0);
+        resample_target(rb, *pr, M, q_in + (size_t)b0 * n, cost_in + b0,
+                        target_keys ? target_keys[t] : (uint32_t)t, q_out + (size_t)(t * Bp) * n);
+    }
+    flush_ops();
+    return 0;
+}
+
 int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* targets,
              const int64_t* offsets, const double* seeds, const uint32_t* target_keys,
              const or_params* pr, double* q_seed, double* errp_seed, double* erro_seed,
@@ -1098,8 +1365,12 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
              int32_t* flag_out, int32_t* n_free, int32_t* solved, int32_t nthreads) {
     Robot rb;
     if (!load_robot(rbi, rb) || !pr || T < 0) return -1;
-    for (int t = 0; t < T; ++t)
+    const bool resample = pr->resample_K > 0;
+    if (resample && pr->resample_B < pr->resample_K) return -1;
+    for (int t = 0; t < T; ++t) {
         if (offsets[t + 1] < offsets[t]) return -1;
+        if (resample && offsets[t + 1] == offsets[t]) return -1;  // nothing to rank
+    }
     Scene sc;
     if (sci) {
         sc.sph.assign(sci->spheres, sci->spheres + 4 * sci->n_spheres);
@@ -1108,6 +1379,8 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
     const or_params p = *pr;
     const int n = rb.n;
     const int k = p.top_k;
+    // seeds polished per target with resampling: floor(B/K) copies of the K best
+    const int Bp = resample ? (p.resample_B / p.resample_K) * p.resample_K : 0;
 
     auto work = [&](int t) {
         Target tg = load_target(targets + 7 * (size_t)t);
@@ -1120,35 +1393,25 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
         or_stage_stats s;
         for (int m = 0; m < M; ++m) {
             double* x = &th[(size_t)m * n];
-            if (seeds)
+            if (seeds) {
                 for (int j = 0; j < n; ++j) x[j] = clip(seeds[(size_t)(b0 + m) * n + j], rb.lo[j], rb.hi[j]);
-            else
+            } else {
+                Unit u(OR_OPS_INIT);
                 uniform_seed(rb, p.rng_seed, (uint32_t)m, tkey, x);
+            }
             po_ccd(rb, tg, p, (uint32_t)m, tkey, x, nullptr, nullptr, s, kHarm);
+            Unit u(OR_OPS_EVAL);
             cst[m] = eval(rb, tg, x).cost;
         }
         // Optional top-K and noisy replication (Alg. HJCD-IK).
         int Mb = M;
         int64_t base = b0;
-        if (p.resample_K > 0) {
-            int K = std::min(p.resample_K, M);
-            int copies = K > 0 ? p.resample_B / K : 0;
-            std::vector<int> idx(M);
-            for (int i = 0; i < M; ++i) idx[i] = i;
-            std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-                if (cst[a] != cst[b]) return cst[a] < cst[b];
-                return a < b;
-            });
-            Mb = copies * K;
-            std::vector<double> nth((size_t)Mb * n);
-            for (int i = 0; i < copies; ++i)
-                for (int kk = 0; kk < K; ++kk) {
-                    double* x = &nth[(size_t)(i * K + kk) * n];
-                    std::memcpy(x, &th[(size_t)idx[kk] * n], sizeof(double) * n);
-                    perturb(rb, p, (uint32_t)(i * K + kk), tkey, ST_RESAMPLE, 0, x);
-                }
+        if (resample) {
+            std::vector<double> nth((size_t)Bp * n);
+            resample_target(rb, p, M, th.data(), cst.data(), tkey, nth.data());
             th.swap(nth);
-            base = (int64_t)t * Mb;
+            Mb = Bp;
+            base = (int64_t)t * Bp;
         }
         // Stage 2: PJ-IK, stage 3: collision filter and selection.
         std::vector<int32_t> fl(Mb);
@@ -1156,13 +1419,20 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
         for (int m = 0; m < Mb; ++m) {
             double* x = &th[(size_t)m * n];
             pj_ik(rb, tg, p, (uint32_t)m, tkey, x, nullptr, nullptr, nullptr, s, kHarm);
-            Res r = eval(rb, tg, x);
+            Res r;
+            {
+                Unit u(OR_OPS_EVAL);
+                r = eval(rb, tg, x);
+            }
             c2[m] = r.cost;
             ep[m] = r.ep;
             eo[m] = r.phi;
             double md;
             int f;
-            collide(rb, sc, x, f, md);
+            {
+                Unit u(OR_OPS_COLLIDE);
+                collide(rb, sc, x, f, md);
+            }
             fl[m] = f;
             if (q_seed) std::memcpy(q_seed + (size_t)(base + m) * n, x, sizeof(double) * n);
             if (errp_seed) errp_seed[base + m] = r.ep;
@@ -1171,7 +1441,10 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
             if (flag_seed) flag_seed[base + m] = f;
         }
         std::vector<int32_t> ord(k);
-        select_order(Mb, fl.data(), c2.data(), k, ord.data());
+        {
+            Unit u(OR_OPS_SELECT);
+            select_order(Mb, fl.data(), c2.data(), k, ord.data());
+        }
         int nf = 0;
         for (int m = 0; m < Mb; ++m) nf += fl[m] == 0;
         int ok = 0;
@@ -1207,8 +1480,31 @@ int or_solve(const or_robot* rbi, const or_scene* sci, int32_t T, const double* 
                 if (t >= T) break;
                 work(t);
             }
+            flush_ops();
         });
     for (auto& th : pool) th.join();
+    return 0;
+}
+
+void or_ops_reset(void) {
+    std::lock_guard<std::mutex> lk(g_ops_mu);
+    for (int c = 0; c < OR_OPS_NCAT; ++c) {
+        g_ops[c] = Ops{0, 0, 0, 0, 0, 0};
+        tl_ops[c] = Ops{0, 0, 0, 0, 0, 0};
+    }
+}
+
+int or_ops_get(int32_t cat, uint64_t* out) {
+    if (cat < 0 || cat >= OR_OPS_NCAT || !out) return -1;
+    flush_ops();
+    std::lock_guard<std::mutex> lk(g_ops_mu);
+    const Ops& o = g_ops[cat];
+    out[0] = o.add;
+    out[1] = o.mul;
+    out[2] = o.div;
+    out[3] = o.sqrt;
+    out[4] = o.trans;
+    out[5] = o.units;
     return 0;
 }
 

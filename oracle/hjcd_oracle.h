@@ -39,6 +39,29 @@ extern "C" {
 
 #define OR_MAX_DOF 32
 
+/* Categories of the operation counts (see or_ops_get).  A unit is one
+ * execution of the step named. */
+enum {
+    OR_OPS_MISC = 0,       /* work outside any unit (inspection calls, target loading) */
+    OR_OPS_EVAL = 1,       /* FK + residual of a configuration: the exit test at the start
+                              of an iteration, the evaluation after a stage */
+    OR_OPS_INIT = 2,       /* one uniform seed */
+    OR_OPS_CD_ITER = 3,    /* one PO-CCD iteration past its exit test: candidates (a full FK
+                              per candidate), greedy picks, combination, acceptance test */
+    OR_OPS_CD_PERTURB = 4, /* one PO-CCD perturbation */
+    OR_OPS_PJ_ITER = 5,    /* one PJ-IK iteration past its exit test: J, W, D, the n x n LM
+                              system, its Cholesky solve, the trust-region clamp */
+    OR_OPS_PJ_TRIAL = 6,   /* one trial configuration: clip + FK + residual + comparison */
+    OR_OPS_PJ_DOGLEG = 7,  /* one dogleg step (its trial is a separate PJ_TRIAL unit) */
+    OR_OPS_PJ_SINGLE = 8,  /* one single-coordinate step (trials separate) */
+    OR_OPS_PJ_PERTURB = 9, /* one PJ-IK perturbation */
+    OR_OPS_RESAMPLE = 10,  /* one replicated seed */
+    OR_OPS_COLLIDE = 11,   /* one configuration's collision test (flat, every pair) */
+    OR_OPS_SELECT = 12,    /* one target's final ordering */
+    OR_OPS_INSTR = 13,     /* test instrumentation (margins, step sensitivity): no unit */
+    OR_OPS_NCAT = 14
+};
+
 typedef struct {
     int32_t dof;                 /* 1..OR_MAX_DOF */
     int32_t convention;          /* 0 = modified DH (Craig), 1 = standard DH */
@@ -85,6 +108,8 @@ typedef struct {
     int32_t n_trials;       /* PJ-IK: trial cost evaluations (line search + dogleg) */
     int32_t n_dogleg;       /* PJ-IK: dogleg steps computed */
     int32_t n_single;       /* PJ-IK: single-coordinate steps computed */
+    int32_t n_tie_pick;     /* PO-CCD: iterations whose tie-tolerant greedy pick (position or
+                               orientation joint) differs from the strict lowest-index argmin */
 } or_stage_stats;
 
 /* ---- kinematics ---------------------------------------------------------- */
@@ -162,6 +187,18 @@ int or_collide(const or_robot* rb, const or_scene* sc, const double* theta, int3
  * index); order[k] receives the first k seed indices (-1 past m). */
 int or_select(int32_t m, const int32_t* flag, const double* cost, int32_t k, int32_t* order);
 
+/* Top-K ranking and noisy replication between the stages (Alg. HJCD-IK) for T
+ * targets: q_in [S*dof] (AoS, CSR offsets[T+1], every target with >= 1 seed),
+ * cost_in [S].  Per target t, its seeds are ranked by (cost, index); with
+ * K = resample_K and B' = floor(resample_B / K) * K, copy i < floor(B/K) of
+ * rank k < K lands at row t*B' + i*K + k of q_out [T*B'*dof] as
+ * clip(q + mu + sigma z), z drawn for seed index i*K + k, stage RESAMPLE,
+ * iteration 0.  A target with fewer than K seeds repeats its ranked seeds
+ * cyclically (rank k takes the seed of rank k mod M).  -1 on invalid input. */
+int or_resample(const or_robot* rb, int32_t T, const int64_t* offsets, const double* q_in,
+                const double* cost_in, const uint32_t* target_keys, const or_params* pr,
+                double* q_out);
+
 /* ---- whole pipeline --------------------------------------------------------
  * T targets (targets[T*7]), CSR seed offsets[T+1], seeds (nullable, AoS
  * [S*dof] doubles; NULL = uniform Philox seeds), target_keys (nullable, [T];
@@ -176,6 +213,15 @@ int or_solve(const or_robot* rb, const or_scene* sc, int32_t T, const double* ta
              const or_params* pr, double* q_seed, double* errp_seed, double* erro_seed,
              double* cost_seed, int32_t* flag_seed, double* q_out, double* err_p, double* err_o,
              int32_t* flag_out, int32_t* n_free, int32_t* solved, int32_t nthreads);
+
+/* ---- operation counts (instrumentation) -------------------------------------
+ * Every FP64 operation the oracle executes is counted in the category of the
+ * unit it belongs to (add / subtract, multiply, divide, square root,
+ * transcendental call; comparisons and sign changes are free).  Totals are
+ * process wide and accumulate over calls until or_ops_reset.
+ * or_ops_get: out[6] = add, mul, div, sqrt, trans, units of category cat. */
+void or_ops_reset(void);
+int or_ops_get(int32_t cat, uint64_t* out);
 
 #ifdef __cplusplus
 }
