@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hjcd_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
-ST_INIT, ST_CD, ST_RESAMPLE, ST_POLISH = 0, 1, 2, 3
+ST_INIT, ST_CD, ST_RESAMPLE, ST_POLISH, ST_WARM = 0, 1, 2, 3, 4
 
 # operation-count categories (hjcd_oracle.h, OR_OPS_*)
 OPS_CATEGORIES = ("misc", "eval", "init", "cd_iter", "cd_perturb", "pj_iter", "pj_trial", "pj_dogleg",
@@ -104,6 +104,10 @@ def lib():
         L.or_select.argtypes = [C.c_int32, ip, dp, C.c_int32, ip]
         L.or_resample.argtypes = [C.POINTER(_Robot), C.c_int32, C.POINTER(C.c_int64), dp, dp, up,
                                   C.POINTER(_Params), dp]
+        L.or_warm_seeds.argtypes = [C.POINTER(_Robot), C.c_int32, C.c_int32, dp, C.c_int32, up,
+                                    C.POINTER(_Params), dp]
+        L.or_select_near.argtypes = [C.c_int32, C.c_int32, ip, dp, dp, dp, dp, dp, C.c_double, C.c_double,
+                                     C.c_int32, ip]
         L.or_ops_reset.argtypes = []
         L.or_ops_reset.restype = None
         L.or_ops_get.argtypes = [C.c_int32, C.POINTER(C.c_uint64)]
@@ -339,6 +343,38 @@ def resample(robot, offsets, q_in, cost_in, p, target_keys=None):
     if rc != 0:
         raise ValueError("or_resample rejected its input")
     return out
+
+
+def warm_seeds(robot, q_prev, k, M, p, target_keys=None):
+    """Tracking warm start: q_prev [T*k, n] previous solutions -> seeds
+    [T*M, n] (seed m of target t from solution m mod k, perturbed for m >= k)."""
+    rh = _rh(robot)
+    n = rh.n
+    qp = _d(np.asarray(q_prev, np.float64).reshape(-1))
+    T = qp.shape[0] // (k * n)
+    tk = None if target_keys is None else np.ascontiguousarray(target_keys, dtype=np.uint32)
+    out = np.zeros((T * M, n))
+    pr = params(p)
+    rc = lib().or_warm_seeds(C.byref(rh.c), T, int(k), _ptr(qp), int(M), _ptr(tk, C.c_uint32), C.byref(pr),
+                             _ptr(out))
+    if rc != 0:
+        raise ValueError("or_warm_seeds rejected its input")
+    return out
+
+
+def select_near(flag, cost, err_p, err_o, q, q_ref, k, succ_pos, succ_ori):
+    """Order of the k seeds nearest to q_ref among the successful ones, then
+    the rest by (flag, cost); q [m, n]."""
+    f = np.ascontiguousarray(flag, dtype=np.int32)
+    m = f.shape[0]
+    qq = _d(np.asarray(q, np.float64).reshape(-1))
+    n = qq.shape[0] // max(m, 1) if m else len(q_ref)
+    o = np.zeros(k, np.int32)
+    rc = lib().or_select_near(m, n, _ptr(f, C.c_int32), _ptr(_d(cost)), _ptr(_d(err_p)), _ptr(_d(err_o)), _ptr(qq),
+                              _ptr(_d(q_ref)), float(succ_pos), float(succ_ori), k, _ptr(o, C.c_int32))
+    if rc != 0:
+        raise ValueError("or_select_near rejected its input")
+    return o
 
 
 # ---------------------------------------------------------------------------

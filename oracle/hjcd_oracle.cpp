@@ -394,7 +394,7 @@ void philox(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
     out[3] = c3;
 }
 
-enum { ST_INIT = 0, ST_CD = 1, ST_RESAMPLE = 2, ST_POLISH = 3 };
+enum { ST_INIT = 0, ST_CD = 1, ST_RESAMPLE = 2, ST_POLISH = 3, ST_WARM = 4 };
 
 // The top 24 bits of a word give a uniform in (0, 1) that is exact in both
 // single and double precision.
@@ -480,6 +480,20 @@ void write_row(double* traj, int row, int n, const double* th, const Res& r) {
 // Per-joint candidates of one PO-CCD iteration k at theta (frames f, residual
 // r): clipped position steps dp, orientation steps dor, and their scores
 // sp = |r_p|^2 and so = |omega|^2 after moving that joint alone.
+// v + (+-a, +-a, +-a) with signs from a xorshift sequence keyed by `key`
+// (shadow runs only).
+V3 jittered(V3 v, double a, uint64_t key) {
+    uint64_t x = key * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    double sg[3];
+    for (int i = 0; i < 3; ++i) {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        sg[i] = (x >> 11) & 1 ? a : -a;
+    }
+    return v3(v.x + sg[0], v.y + sg[1], v.z + sg[2]);
+}
+
 void cd_candidates(const Robot& rb, const Target& tg, const or_params& p, const double* th, int k,
                    const FK& f, const Res& r, double* dp, double* dor, double* sp, double* so,
                    Margin& mg, double harm) {
@@ -497,15 +511,25 @@ void cd_candidates(const Robot& rb, const Target& tg, const or_params& p, const 
         V3 v = tg.p - f.P[j];
         V3 up = u - dot(u, z) * z;
         V3 vp = v - dot(v, z) * z;
+        if (p.shadow) {
+            // shadow run: the projections carry single-precision-sized
+            // absolute errors (positions of order 1 m)
+            Scope instr(OR_OPS_INSTR);
+            up = jittered(up, 1.2e-7, p.shadow * 7919ull + (uint64_t)(k * 64 + j) * 2);
+            vp = jittered(vp, 1.2e-7, p.shadow * 7919ull + (uint64_t)(k * 64 + j) * 2 + 1);
+        }
         double du = norm(up), dv = norm(vp);
         double d = 0.0;
         if (du >= p.proj_eps && dv >= p.proj_eps) {
             V3 uh = (1.0 / du) * up, vh = (1.0 / dv) * vp;
             double c = clip(dot(uh, vh), -1.0, 1.0);
             double mag = std::acos(c);
-            double sgn = dot(z, cross(uh, vh)) >= 0.0 ? 1.0 : -1.0;
+            const double sn = dot(z, cross(uh, vh));
+            double sgn = sn >= 0.0 ? 1.0 : -1.0;
             d = sgn * mag;
             ops(0, 1, 2, 0, 1);
+            // the turning direction is a decision when the step is not ~0
+            if (mag > harm) mg.add(std::fabs(sn));
         }
         mg.add(std::fabs(du - p.proj_eps));
         mg.add(std::fabs(dv - p.proj_eps));
@@ -1338,6 +1362,65 @@ void resample_target(const Robot& rb, const or_params& p, int M, const double* t
             std::memcpy(x, th + (size_t)idx[kk % M] * n, sizeof(double) * n);
             perturb(rb, p, (uint32_t)(i * K + kk), tkey, ST_RESAMPLE, 0, x);
         }
+}
+
+// Warm start for a target on a path (Sec. V, the hardware demonstration:
+// each pose is solved from the solution set of the previous one): seed m of
+// target t starts at previous solution m mod k, unchanged for m < k and
+// moved by clip(. + mu + sigma z) otherwise, z drawn for seed index m at
+// stage WARM, iteration 0.
+int or_warm_seeds(const or_robot* rbi, int32_t T, int32_t k, const double* q_prev, int32_t M,
+                  const uint32_t* target_keys, const or_params* pr, double* q_out) {
+    Robot rb;
+    if (!load_robot(rbi, rb) || !pr || T < 0 || k < 1 || M < 0) return -1;
+    const int n = rb.n;
+    for (int t = 0; t < T; ++t) {
+        const uint32_t tkey = target_keys ? target_keys[t] : (uint32_t)t;
+        for (int m = 0; m < M; ++m) {
+            const double* src = q_prev + (size_t)(t * k + m % k) * n;
+            double* x = q_out + ((size_t)t * M + m) * n;
+            for (int j = 0; j < n; ++j) x[j] = clip(src[j], rb.lo[j], rb.hi[j]);
+            if (m >= k) perturb(rb, *pr, (uint32_t)m, tkey, ST_WARM, 0, x);
+        }
+    }
+    flush_ops();
+    return 0;
+}
+
+// Selection nearest to a reference configuration (the tracking variant of the
+// final selection): seeds that are collision free with err_p <= succ_pos and
+// err_o <= succ_ori come first, ordered by squared joint distance to q_ref;
+// every other seed follows in the (flag, cost) order; ties go to the lower
+// index.
+int or_select_near(int32_t m, int32_t dof, const int32_t* flag, const double* cost, const double* err_p,
+                   const double* err_o, const double* q, const double* q_ref, double succ_pos, double succ_ori,
+                   int32_t k, int32_t* order) {
+    if (m < 0 || k < 0 || dof < 1) return -1;
+    std::vector<int> cls(m);
+    std::vector<double> key(m);
+    for (int i = 0; i < m; ++i) {
+        const bool ok = flag[i] == 0 && err_p[i] <= succ_pos && err_o[i] <= succ_ori;
+        cls[i] = ok ? 0 : (flag[i] == 0 ? 1 : 2);
+        if (ok) {
+            double d2 = 0.0;
+            for (int j = 0; j < dof; ++j) {
+                const double dj = q[(size_t)i * dof + j] - q_ref[j];
+                d2 += dj * dj;
+            }
+            key[i] = d2;
+        } else {
+            key[i] = cost[i];
+        }
+    }
+    std::vector<int> idx(m);
+    for (int i = 0; i < m; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (cls[a] != cls[b]) return cls[a] < cls[b];
+        if (key[a] != key[b]) return key[a] < key[b];
+        return a < b;
+    });
+    for (int i = 0; i < k; ++i) order[i] = i < m ? idx[i] : -1;
+    return 0;
 }
 
 int or_resample(const or_robot* rbi, int32_t T, const int64_t* offsets, const double* q_in,

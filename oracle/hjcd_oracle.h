@@ -95,8 +95,11 @@ typedef struct {
     double succ_pos, succ_ori;
     uint64_t rng_seed;
     /* Test instrumentation, 0 = off: PJ-IK linearises with J and e carrying
-     * single-precision-sized pseudo-random errors drawn from this key (a
-     * "shadow" run that shows how far rounding alone can move a trajectory). */
+     * single-precision-sized pseudo-random errors drawn from this key, and
+     * PO-CCD projects its position candidates from joint-to-EE and
+     * joint-to-target vectors carrying single-precision-sized absolute
+     * errors (a "shadow" run that shows how far rounding alone can move a
+     * trajectory). */
     uint64_t shadow;
 } or_params;
 
@@ -198,6 +201,22 @@ int or_select(int32_t m, const int32_t* flag, const double* cost, int32_t k, int
 int or_resample(const or_robot* rb, int32_t T, const int64_t* offsets, const double* q_in,
                 const double* cost_in, const uint32_t* target_keys, const or_params* pr,
                 double* q_out);
+
+/* Warm start for a target on a path (tracking, Sec. V demonstration): q_prev
+ * [T*k*dof] holds each target's k previous solutions; seed m < M of target t
+ * (row t*M + m of q_out [T*M*dof]) is previous solution m mod k clipped to the
+ * limits, and for m >= k additionally moved by clip(. + mu + sigma z), z
+ * drawn for seed index m, stage WARM (4), iteration 0.  -1 on invalid input. */
+int or_warm_seeds(const or_robot* rb, int32_t T, int32_t k, const double* q_prev, int32_t M,
+                  const uint32_t* target_keys, const or_params* pr, double* q_out);
+
+/* Selection nearest to a reference configuration q_ref[dof] over m seeds
+ * (q [m*dof]): seeds with flag 0, err_p <= succ_pos and err_o <= succ_ori
+ * first, by squared joint distance to q_ref; then collision-free seeds, then
+ * colliding ones, each by cost; ties -> lower index.  order[k] as or_select. */
+int or_select_near(int32_t m, int32_t dof, const int32_t* flag, const double* cost, const double* err_p,
+                   const double* err_o, const double* q, const double* q_ref, double succ_pos, double succ_ori,
+                   int32_t k, int32_t* order);
 
 /* ---- whole pipeline --------------------------------------------------------
  * T targets (targets[T*7]), CSR seed offsets[T+1], seeds (nullable, AoS
