@@ -1,26 +1,32 @@
-"""Benchmark of the batched HJCD-IK solve on one MI355X.
+"""Benchmark of batched and served HJCD-IK on one MI355X.
 
-One step = one hjcd_solve over the whole batch (seed init, PO-CCD, PJ-IK,
-collision filter, top-k selection) with every input resident in HBM.
-Workload: Panda-like 7-DoF chain, 1,000 targets x 1,024 seeds, 60 link
-spheres, 32 obstacle spheres, top-8 (the batched configuration).
+Prints one JSON line.  The headline is the serving workload: a Poisson
+stream of IK requests (1-16 Panda-like targets each, 32-1,024 seeds per
+target, the 32-sphere scene of the batched workload) at 10,000 requests/s,
+served by the continuous-batching server; `value` = collision-free solves
+per second at 1 mm / 1 deg over a 10 s window that follows a 1 s warm-up,
+with p50 / p99 request latency beside it.  The plain form (one hjcd_solve
+launch sequence per request) runs the same first requests of the stream, and
+`speedup_vs_plain` compares both modes on that same request set.  The other
+rates (2,000 and 50,000 requests/s) are reported the same way.
 
-Prints one JSON line.  `value` = collision-free solves per second at 1 mm /
-1 deg (targets with a returned collision-free seed within tolerance, per
-second of wall time).  `roofline` prices the dominant kernel, PJ-IK
-(k_polish), by its algorithmic FP32 flops (per-unit counts x executed units,
-counted live by the kernel) against the MI355X FP32 vector peak, with the
-PO-CCD kernel's figures beside it; `cpu_baseline` times the FP64 oracle on a
-bounded sample of the same workload on the host cores.  Further sections:
-the uneven multi-robot batch (eager vs graph plan), the serving streams
-(served vs plain) and, with --large, the 100,000 x 256 20-joint workload.
+`steps` / `ms_per_step` time K whole hjcd_solve calls of the batched
+workload (1,000 targets x 1,024 seeds, top-8, inputs resident in HBM), whose
+PJ-IK kernel (`k_polish`) is priced in `roofline`: the oracle's FP64
+operation counts per executed unit of work (measured in the CPU-baseline run
+on the same workload) x the units the kernel counts in the timed launches,
+over the kernel's HIP-event time on its stream, against the FP32 vector peak.
+Further sections: the uneven three-robot batch (eager solve vs graph plan),
+the large 20-joint workload (100,000 x 256), the DoF-scaling chains and the
+8 x 64 tiny solve.  `cpu_baseline` times the FP64 oracle on a bounded sample
+of the batched workload on the host cores (and single-threaded).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -33,52 +39,17 @@ if ROOT not in sys.path:
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (AMD public spec)
 PEAK_HBM_GBS = 8000.0
 
-
-# ---------------------------------------------------------------------------
-# Algorithmic FP32 flops of the per-seed solve kernels per executed unit.
-# Counted from the kernel's arithmetic (add/mul = 1, fma = 2, each
-# transcendental sin / cos / atan2 / sqrt / log / div = 1); see the design doc.
-# ---------------------------------------------------------------------------
-def fk_flops(n, modified=True, tool_rot=False):
-    return (57 if modified else 51) * n + 18 + (45 if tool_rot else 0)
-
-
-RESIDUAL = 64 + 3  # residual + cost
-
-
-def unit_flops(n, modified=True, tool_rot=False):
-    fk = fk_flops(n, modified, tool_rot)
-    return dict(
-        cd_iter=fk + RESIDUAL + 6 + 116 * n + 178,
-        pol_iter=fk + RESIDUAL + 669 + 110 * n,
-        pol_trial=fk + RESIDUAL + 2 * n + 1,
-        pol_dogleg=94 * n + 200,
-        pol_single=36 * n + 2,
-        perturb=9 * n,
-        seed=5 * n + 2 * (fk + RESIDUAL + 1),  # seed init + final FK of both stages
-    )
-
-
-def stage_flops(n, st, modified=True, tool_rot=False):
-    """(PO-CCD kernel, PJ-IK kernel) algorithmic flops of one solve."""
-    u = unit_flops(n, modified, tool_rot)
-    final = fk_flops(n, modified, tool_rot) + RESIDUAL + 1
-    cd = st["cd_iters"] * u["cd_iter"] + st["cd_perturb"] * u["perturb"] + st["seeds"] * (5 * n + final)
-    pol = (st["pol_iters"] * u["pol_iter"] + st["pol_trials"] * u["pol_trial"] + st["pol_dogleg"] * u["pol_dogleg"]
-           + st["pol_single"] * u["pol_single"] + st["pol_perturb"] * u["perturb"] + st["seeds"] * final)
-    return cd, pol
-
-
-def algorithmic_flops(n, st, modified=True, tool_rot=False):
-    u = unit_flops(n, modified, tool_rot)
-    return (st["cd_iters"] * u["cd_iter"] + st["pol_iters"] * u["pol_iter"]
-            + st["pol_trials"] * u["pol_trial"] + st["pol_dogleg"] * u["pol_dogleg"]
-            + st["pol_single"] * u["pol_single"]
-            + (st["cd_perturb"] + st["pol_perturb"]) * u["perturb"] + st["seeds"] * u["seed"])
-
-
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_polish_batched_panda_1000x1024_traffic.txt")
 KERNEL_SOURCES = ("hjcd_device.hpp", "hjcd_launch.hpp", "hjcd_solve_inst.hip")
+
+# executed units the PJ-IK kernel counts -> the oracle's operation category of
+# the same unit (an iteration is one evaluation (FK, Jacobian inputs,
+# residual) plus the LM linearisation and step; every seed is evaluated once
+# more for its final state)
+POLISH_UNITS = (("pol_iters", ("eval", "pj_iter")), ("pol_trials", ("pj_trial",)),
+                ("pol_dogleg", ("pj_dogleg",)), ("pol_single", ("pj_single",)),
+                ("pol_perturb", ("pj_perturb",)), ("seeds", ("eval",)))
+CD_UNITS = (("cd_iters", ("eval", "cd_iter")), ("cd_perturb", ("cd_perturb",)), ("seeds", ("init", "eval")))
 
 
 def kernel_sources_sha():
@@ -106,29 +77,76 @@ def measured_traffic():
     return int(float(kv["traffic_bytes_per_launch"]))
 
 
-def cpu_baseline(batch, n_targets):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(batch, n_targets, n_single):
     """FP64 oracle on the first n_targets targets of the batch (all their
-    seeds, uniform Philox seeds like the GPU run), all host cores."""
+    seeds, uniform Philox seeds like the GPU run) on the host cores, and on
+    the first n_single targets single-threaded.  Also returns the oracle's
+    operation counts per executed unit of work (Alg. PO-CCD / PJ-IK units),
+    counted in the multi-threaded run."""
     import oracle as O
     rob = batch.robots[0]
-    sub_q = batch.q_star[:n_targets]
-    tg = O.targets_from_qstar(rob, sub_q).astype(np.float64)
     M = int(batch.seed_offsets[1] - batch.seed_offsets[0])
-    offs = np.arange(n_targets + 1, dtype=np.int64) * M
-    cores = os.cpu_count() or 1
-    t0 = time.perf_counter()
-    out = O.solve(rob, batch.scene, tg, offs, batch.params, seeds=None, nthreads=cores)
-    dt = time.perf_counter() - t0
-    solved = int(out["solved"].sum())
-    return {"value": solved / dt, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n_targets} of {batch.T} targets x {M} seeds, FP64, {dt:.1f} s wall",
-            "solved": solved, "seconds": dt}
+
+    def run(nt, threads):
+        tg = O.targets_from_qstar(rob, batch.q_star[:nt]).astype(np.float64)
+        offs = np.arange(nt + 1, dtype=np.int64) * M
+        t0 = time.perf_counter()
+        out = O.solve(rob, batch.scene, tg, offs, batch.params, seeds=None, nthreads=threads)
+        return int(out["solved"].sum()), time.perf_counter() - t0
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    O.ops_reset()
+    solved, dt = run(n_targets, cores)
+    ops = O.ops_get()
+    solved1, dt1 = run(n_single, 1)
+    per_unit = {k: {"flops": v["flops"] / v["units"], "transcendental": v["trans"] / v["units"]}
+                for k, v in ops.items() if v["units"] > 0}
+    return {"value": round(solved / dt, 2), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_targets} of {batch.T} targets x {M} seeds of {batch.name}, FP64, {dt:.1f} s wall",
+            "cpu_model": cpu_model(), "solved": solved, "seconds": round(dt, 2),
+            "single_thread": {"value": round(solved1 / dt1, 3), "unit": "solves/s", "cores": 1,
+                              "sample": f"first {n_single} targets x {M} seeds, {dt1:.1f} s wall",
+                              "targets_per_s": round(n_single / dt1, 3)}}, per_unit
+
+
+def unit_flops(per_unit, units):
+    """flops and transcendental calls per unit kind from the oracle's
+    per-unit counts."""
+    out = {}
+    for name, cats in units:
+        out[name] = (sum(per_unit.get(c, {}).get("flops", 0.0) for c in cats),
+                     sum(per_unit.get(c, {}).get("transcendental", 0.0) for c in cats))
+    return out
+
+
+def algorithmic(per_unit, units, st):
+    """(flops, transcendental calls) of one launch: executed units x the
+    oracle's operation counts per unit."""
+    f = t = 0.0
+    for name, (uf, ut) in unit_flops(per_unit, units).items():
+        f += st[name] * uf
+        t += st[name] * ut
+    return f, t
 
 
 def measure(H, ctx, torch, batch, steps, warmup):
     """Time `steps` whole hjcd_solve calls on one single-robot batch with
-    inputs resident in HBM; the k_solve time comes from the library's HIP
-    events on the launch stream."""
+    inputs resident in HBM; stage times come from the library's HIP events
+    on the launch stream, executed units from the kernels' counters."""
     rob = batch.robots[0]
     n, T, k = rob.dof, batch.T, batch.params["top_k"]
     dev = torch.device("cuda:0")
@@ -157,15 +175,13 @@ def measure(H, ctx, torch, batch, steps, warmup):
         step()
     stream.synchronize()
     torch.cuda.synchronize()
-    kern_ms, step_ms = [], []
-    agg = None
+    step_ms, agg = [], None
     t_start = time.perf_counter()
     for _ in range(steps):
         t0 = time.perf_counter()
         step()
         st = H.hjcd_get_stats(ctx)  # waits for this step's last event on `stream`
         step_ms.append((time.perf_counter() - t0) * 1e3)
-        kern_ms.append(st["ms_polish"])
         if agg is None:
             agg = {kk: 0 for kk in st}
         for kk, v in st.items():
@@ -174,29 +190,49 @@ def measure(H, ctx, torch, batch, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     n_solved = int(sv.sum().item())
+    best_ep = ep.view(T, k)[:, 0].cpu().numpy()
+    best_eo = eo.view(T, k)[:, 0].cpu().numpy()
     ms_per_step = wall * 1e3 / steps
     per_step = {kk: v / steps for kk, v in agg.items()}
-    f_cd, f_pol = stage_flops(n, per_step)
-    kavg = float(np.mean(kern_ms))
-    achieved = f_pol / (kavg * 1e-3) / 1e12
-    cd_ms = per_step["ms_cd"]
-    roof = {"bound": "alu", "kernel": f"k_polish (PJ-IK, {n} joints)", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None, "kernel_ms": round(kavg, 4), "algorithmic_gflop_per_launch": round(f_pol / 1e9, 3),
-            "cd_kernel": {"kernel": "k_cd (PO-CCD)", "kernel_ms": round(cd_ms, 4),
-                          "algorithmic_gflop_per_launch": round(f_cd / 1e9, 3),
-                          "achieved": round(f_cd / (cd_ms * 1e-3) / 1e12, 3) if cd_ms > 0 else None},
-            "both_stages_achieved": round((f_cd + f_pol) / ((kavg + cd_ms) * 1e-3) / 1e12, 3)}
+    rb.close()
+    sc.close()
     return {"value": round(n_solved / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 3),
             "solved_targets": n_solved, "success_rate": round(n_solved / T, 4),
+            "best_err_median": {"pos_m": float(np.median(best_ep)), "ori_rad": float(np.median(best_eo))},
             "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                            "p99": round(float(np.percentile(step_ms, 99)), 3)},
             "stage_ms": {kk: round(per_step[kk], 4) for kk in
                          ("ms_cd", "ms_resample", "ms_polish", "ms_collide", "ms_select", "ms_total")},
             "work_per_step": {kk: int(per_step[kk]) for kk in
                               ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
-                               "pol_single", "pol_perturb", "coll_coarse", "coll_fine")},
-            "roofline": roof}
+                               "pol_single", "pol_perturb", "coll_coarse", "coll_fine")}}
+
+
+def roofline(m, per_unit, n):
+    """The PJ-IK kernel's algorithmic FP32 rate (oracle operation counts per
+    executed unit x the units of one launch / the kernel's event time)."""
+    w = m["work_per_step"]
+    roof = {"bound": "alu", "kernel": f"k_polish (PJ-IK, {n} joints)", "workload": m["workload"],
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "kernel_ms": m["stage_ms"]["ms_polish"],
+            "traffic": measured_traffic()}
+    if per_unit is None:
+        roof.update(achieved=None, frac=None, note="no oracle operation counts (--no-cpu)")
+        return roof
+    f_pol, t_pol = algorithmic(per_unit, POLISH_UNITS, w)
+    f_cd, t_cd = algorithmic(per_unit, CD_UNITS, w)
+    kms = m["stage_ms"]["ms_polish"]
+    cms = m["stage_ms"]["ms_cd"]
+    ach = f_pol / (kms * 1e-3) / 1e12
+    roof.update(achieved=round(ach, 3), frac=round(ach / PEAK_FP32_TFLOPS, 4),
+                algorithmic_gflop_per_launch=round(f_pol / 1e9, 3),
+                transcendental_g_per_launch=round(t_pol / 1e9, 4),
+                flops_per_unit={kk: round(v[0], 1) for kk, v in unit_flops(per_unit, POLISH_UNITS).items()},
+                frac_of_unpacked_fma_rate=round(ach / (PEAK_FP32_TFLOPS / 2), 4),
+                cd_kernel={"kernel": "k_cd (PO-CCD)", "kernel_ms": cms,
+                           "algorithmic_gflop_per_launch": round(f_cd / 1e9, 3),
+                           "achieved": round(f_cd / (cms * 1e-3) / 1e12, 3) if cms > 0 else None,
+                           "flops_per_unit": {kk: round(v[0], 1) for kk, v in unit_flops(per_unit, CD_UNITS).items()}})
+    return roof
 
 
 def uneven(H, ctx, torch, steps, log):
@@ -254,13 +290,138 @@ def uneven(H, ctx, torch, steps, log):
     return row
 
 
-def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
-    """Poisson request streams served by the continuous-batching server and
-    by the plain one-request-per-launch server (same requests, same keys)."""
+def dof_scaling(H, ctx, torch, log):
+    """The chained Panda-like robots (7, 12, 18, 24 DoF, open world, B =
+    1,000 seeds per target): throughput of a 1,000-target batch and the
+    latency of a one-target solve."""
+    from paper_2510_07514_amd import workload as W
+    rows = []
+    for dof in (7, 12, 18, 24):
+        b = W.config_dof(dof)
+        mb = measure(H, ctx, torch, b, 3, 1)
+        one = W.config_dof(dof, T=1)
+        m1 = measure(H, ctx, torch, one, 30, 3)
+        row = {"dof": dof, "robot": b.robots[0].name, "seeds_per_target": 1000,
+               "batch_1000_targets": {"ms_per_solve": mb["ms_per_step"], "solves_per_s": mb["value"],
+                                      "success_rate": mb["success_rate"], "stage_ms": mb["stage_ms"]},
+               "one_target": {"ms_p50": m1["latency_ms"]["p50"], "ms_p99": m1["latency_ms"]["p99"],
+                              "solved": m1["solved_targets"]}}
+        log(f"dof scaling: {row}")
+        rows.append(row)
+    return rows
+
+
+def resampling(H, ctx, torch, batch, log):
+    """Paper-mode resampling (Alg. HJCD-IK: PO-CCD on all M seeds, then
+    floor(B/K) noisy copies of the K best polished) on the batched workload,
+    against K = B = M (every CD seed polished): latency and accuracy."""
+    rows = []
+    M = int(batch.seed_offsets[1] - batch.seed_offsets[0])
+    for K, B in [(0, 0)] + [(K, B) for K in (8, 32, 128) for B in (64, 256, 1000) if B >= K]:
+        b = batch
+        b.params = dict(batch.params, resample_K=K, resample_B=B)
+        m = measure(H, ctx, torch, b, 5, 1)
+        Bp = (B // K) * K if K else M
+        rows.append({"K": K if K else M, "B": B if K else M, "polished_per_target": Bp,
+                     "ms_per_solve": m["ms_per_step"], "solves_per_s": m["value"], "success_rate": m["success_rate"],
+                     "best_err_median": m["best_err_median"],
+                     "stage_ms": {kk: m["stage_ms"][kk] for kk in ("ms_cd", "ms_resample", "ms_polish", "ms_collide")}})
+        log(f"resampling: {rows[-1]}")
+    batch.params = dict(batch.params, resample_K=0, resample_B=0)
+    return rows
+
+
+def tracking(H, ctx, torch, log, tracks=256, steps=100, M=64, k=8, cold_M=1024):
+    """Poses along paths (Sec. V demonstration): 256 Panda-like tracks (the
+    batched workload's robot and scene), 100 poses each; every pose solved
+    from the previous pose's 8 solutions (64 warm seeds) with the nearest-
+    solution selection, against the cost selection on the same warm seeds and
+    a cold start (1,024 uniform seeds) per pose."""
+    from paper_2510_07514_amd import workload as W
+    b = W.config_batched(T=1, M=1)
+    rob = b.robots[0]
+    n = rob.dof
+    paths = W.tracking_paths(rob, tracks, steps)
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    qd = torch.as_tensor(np.ascontiguousarray(paths.reshape(-1, n).T)).cuda()
+    pose = torch.zeros(7, steps * tracks, device="cuda")
+    H.hjcd_fk(ctx, rb, qd, pose, None)
+    torch.cuda.synchronize()
+    targets = [pose[:, s * tracks:(s + 1) * tracks].contiguous() for s in range(steps)]
+    stream = torch.cuda.Stream()
+    out = {}
+    for mode in ("near", "cost", "cold"):
+        p = H.params_from_dict(dict(b.params, top_k=k, rng_seed=9))
+        MM = cold_M if mode == "cold" else M
+        offs = np.arange(tracks + 1, dtype=np.int64) * MM
+        o = [torch.zeros(tracks * k, n, device="cuda"), torch.zeros(tracks * k, device="cuda"),
+             torch.zeros(tracks * k, device="cuda"), torch.zeros(tracks * k, dtype=torch.uint8, device="cuda"),
+             torch.zeros(tracks, dtype=torch.int32, device="cuda"), torch.zeros(tracks, dtype=torch.uint8, device="cuda")]
+        prev = torch.as_tensor(np.repeat(paths[0], k, axis=0)).cuda()
+        ref = torch.as_tensor(paths[0]).cuda()
+        seeds = torch.zeros(n, tracks * MM, device="cuda")
+        chosen, lat, solved = [paths[0]], [], 0
+        for s in range(1, steps):
+            keys = torch.as_tensor((np.arange(tracks) + s * tracks).astype(np.int32)).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "cold":
+                H.hjcd_solve(ctx, [rb], sc, targets[s], offs, p, *o, target_keys=keys, stream=stream)
+            else:
+                H.hjcd_warm_seeds(ctx, rb, prev, k, MM, p, seeds, target_keys=keys, stream=stream)
+                if mode == "near":
+                    H.hjcd_solve_near(ctx, [rb], sc, targets[s], offs, p, ref, *o, seeds=seeds, target_keys=keys,
+                                      stream=stream)
+                else:
+                    H.hjcd_solve(ctx, [rb], sc, targets[s], offs, p, *o, seeds=seeds, target_keys=keys, stream=stream)
+            stream.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+            solved += int(o[5].sum().item())
+            prev = o[0].clone()
+            ref = o[0].view(tracks, k, n)[:, 0].contiguous()
+            chosen.append(ref.cpu().numpy())
+        ch = np.asarray(chosen)
+        move = np.abs(np.diff(ch, axis=0)).max(axis=2)
+        out[mode] = {"seeds_per_pose": MM, "ms_per_pose_p50": round(float(np.percentile(lat, 50)), 3),
+                     "ms_per_pose_p99": round(float(np.percentile(lat, 99)), 3),
+                     "success_rate": round(solved / (tracks * (steps - 1)), 4),
+                     "joint_move_per_step_rad": {"median": round(float(np.median(move)), 4),
+                                                 "p99": round(float(np.percentile(move, 99)), 4),
+                                                 "max": round(float(move.max()), 3)},
+                     "steps_moving_over_0.5_rad": int((move > 0.5).sum())}
+        log(f"tracking {mode}: {out[mode]}")
+    rb.close()
+    sc.close()
+    return {"workload": f"tracking_panda_{tracks}_tracks_x_{steps}_poses", "top_k": k, "modes": out}
+
+
+def _window_stats(info, mask, t0=None):
+    """solves/s, p50 / p99 latency over the completed requests selected by
+    `mask` (solves/s = targets solved / (last completion - start), start =
+    t0 or the first arrival)."""
+    sel = info[mask]
+    if sel.shape[0] == 0:
+        return {"requests": 0}
+    lat = (sel["done_s"] - sel["arrival_s"]) * 1e3
+    start = float(sel["arrival_s"].min()) if t0 is None else t0
+    span = float(sel["done_s"].max()) - start
+    solved = int(sel["n_solved"].sum())
+    return {"requests": int(sel.shape[0]), "targets": int(sel["n_targets"].sum()), "targets_solved": solved,
+            "solves_per_s": round(solved / span, 1) if span > 0 else None,
+            "p50_latency_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 3), "span_s": round(span, 3)}
+
+
+def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, log):
+    """Poisson request streams: the continuous-batching server on the whole
+    stream (warm-up + window; statistics over the requests that arrive in the
+    window) and both modes on the stream's first `prefix` requests (the same
+    requests, same keys)."""
     from paper_2510_07514_amd import workload as W
     out = []
-    for rate in rates:
-        s = W.serving_stream(float(rate), duration)
+    for ri, rate in enumerate(rates):
+        s = W.serving_stream(float(rate), warm + window)
         rob, scene = s["robot"], s["scene"]
         rb = H.hjcd_load_robot(ctx, rob)
         sc = H.hjcd_load_scene(ctx, scene.spheres, scene.boxes)
@@ -272,14 +433,16 @@ def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
         H.hjcd_fk(ctx, rb, qd, pose, None)
         torch.cuda.synchronize()
         poses = pose.cpu().numpy().T.copy()
+        del qd, pose
         offs = np.concatenate([[0], np.cumsum(s["n_targets"])])
         params = H.params_from_dict(s["params"])
+        n_pre = min(n_req, prefix)
         row = {"rate_req_s": rate, "requests": int(n_req), "targets": int(offs[-1]),
-               "mean_seeds_per_target": round(float(np.mean(s["seeds_per_target"])), 1)}
-        if rate == rates[0]:
-            # warm-up: the first requests of the stream through both modes, so
-            # that kernel loading and first-touch allocation stay out of the
-            # measured windows
+               "mean_targets_per_request": round(float(np.mean(s["n_targets"])), 2),
+               "mean_seeds_per_target": round(float(np.mean(s["seeds_per_target"])), 1),
+               "window_s": window, "warmup_s": warm, "same_prefix_requests": int(n_pre)}
+        if ri == 0:
+            # kernel loading and first-touch allocation outside every measurement
             for mode in (H.HJCD_SERVE_BATCHED, H.HJCD_SERVE_PLAIN):
                 srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk)
                 for i in range(min(n_req, 32)):
@@ -288,27 +451,34 @@ def serving(H, ctx, torch, rates, duration, slots, chunk, plain_cap, log):
                 H.hjcd_server_start(srv)
                 H.hjcd_server_wait(srv, 120.0)
                 srv.close()
-        for mode, name in ((H.HJCD_SERVE_BATCHED, "served"), (H.HJCD_SERVE_PLAIN, "plain")):
-            m = n_req if mode == H.HJCD_SERVE_BATCHED else min(n_req, plain_cap)
+        infos = {}
+        for mode, name, m in ((H.HJCD_SERVE_BATCHED, "served", n_req), (H.HJCD_SERVE_PLAIN, "plain", n_pre)):
             srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk,
-                                       max_queue=n_req + 1)
+                                       max_queue=m + 1)
             for i in range(m):
                 H.hjcd_server_submit(srv, poses[offs[i]:offs[i + 1]], int(s["seeds_per_target"][i]), int(offs[i]),
                                      float(s["arrival"][i]))
             t0 = time.perf_counter()
             H.hjcd_server_start(srv)
-            H.hjcd_server_wait(srv, 600.0)
+            H.hjcd_server_wait(srv, 900.0)
             wall = time.perf_counter() - t0
             st = H.hjcd_server_get_stats(srv)
+            info = H.hjcd_server_poll_all(srv)
             srv.close()
-            row[name] = {"requests": m, "solves_per_s": round(st["solves_per_s"], 1),
-                         "p50_latency_ms": round(st["p50_latency_ms"], 3),
-                         "p99_latency_ms": round(st["p99_latency_ms"], 3),
-                         "targets_solved": int(st["targets_solved"]), "targets_done": int(st["targets_done"]),
-                         "chunks": int(st["chunks"]), "mean_resident_slots": round(st["mean_resident_slots"], 1),
-                         "wall_s": round(wall, 3)}
-            log(f"serving {name} at {rate} req/s: {row[name]}")
-        row["speedup_solves_per_s"] = round(row["served"]["solves_per_s"] / max(row["plain"]["solves_per_s"], 1e-9), 2)
+            info = info[np.argsort(info["tag"], kind="stable")]  # tag = first target index: arrival order
+            infos[name] = info
+            log(f"serving {name} at {rate} req/s: {m} requests in {wall:.1f} s, {int(st['chunks'])} chunks")
+            if name == "served":
+                row["served_window"] = dict(_window_stats(info, info["arrival_s"] >= warm, t0=warm),
+                                            chunks=int(st["chunks"]),
+                                            mean_resident_slots=round(st["mean_resident_slots"], 1),
+                                            resident_slots_peak=int(st["resident_slots_peak"]))
+        pre = np.arange(n_req) < n_pre
+        row["served_same_prefix"] = _window_stats(infos["served"], pre)
+        row["plain_same_prefix"] = _window_stats(infos["plain"], np.ones(infos["plain"].shape[0], bool))
+        a, b = row["served_same_prefix"]["solves_per_s"], row["plain_same_prefix"]["solves_per_s"]
+        row["speedup_vs_plain"] = round(a / b, 2) if a and b else None
+        log(f"serving at {rate} req/s: {json.dumps(row)}")
         out.append(row)
         rb.close()
         sc.close()
@@ -322,22 +492,29 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--targets", type=int, default=1000)
     ap.add_argument("--seeds", type=int, default=1024)
-    ap.add_argument("--cpu-targets", type=int, default=512)
+    ap.add_argument("--cpu-targets", type=int, default=384)
+    ap.add_argument("--cpu-single-targets", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 100,000 x 256 random 20-joint workload")
+    ap.add_argument("--no-dof", action="store_true", help="skip the DoF-scaling chains")
+    ap.add_argument("--no-resample", action="store_true", help="skip the paper-mode resampling sweep")
+    ap.add_argument("--no-tracking", action="store_true", help="skip the path-tracking runs")
     ap.add_argument("--no-tiny", action="store_true", help="skip the 8 x 64 latency case (profiling runs)")
-    ap.add_argument("--large", action="store_true", help="also time the 100,000 x 256 random 20-joint workload")
     ap.add_argument("--serve-rates", default="2000,10000,50000")
-    ap.add_argument("--serve-duration", type=float, default=1.0, help="seconds of each request stream")
+    ap.add_argument("--headline-rate", type=int, default=10000)
+    ap.add_argument("--serve-window", type=float, default=10.0, help="seconds of each measured request window")
+    ap.add_argument("--serve-warmup", type=float, default=1.0, help="seconds of stream before the window")
+    ap.add_argument("--serve-prefix", type=int, default=10000,
+                    help="first requests of each stream run by both modes (the same-request comparison)")
     ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
     ap.add_argument("--serve-chunk", type=int, default=4, help="iterations per serving chunk")
-    ap.add_argument("--plain-cap", type=int, default=4000, help="requests of each stream the plain server runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve has no multi-GPU path",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
@@ -357,40 +534,61 @@ def main():
     from paper_2510_07514_amd import hjcd as H
     from paper_2510_07514_amd import workload as W
 
-    batch = W.config_batched(T=args.targets, M=args.seeds, host_seeds=False)
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     ctx = H.hjcd_ctx_create(0)
+    batch = W.config_batched(T=args.targets, M=args.seeds, host_seeds=False)
     m = measure(H, ctx, torch, batch, args.steps, args.warmup)
+    m["workload"] = f"batched_panda_{batch.T}x{args.seeds}"
+    log(f"batched: {json.dumps(m)}")
     rob = batch.robots[0]
-    n, T, k = rob.dof, batch.T, batch.params["top_k"]
-    steps = args.steps
     line = {
-        "metric": "collision-free IK solves/s at 1mm/1deg",
-        "value": m["value"],
+        "metric": "collision-free IK solves/s at 1mm/1deg + p50/p99 latency, served vs plain",
+        "value": None,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": m["ms_per_step"],
+        "step_workload": m["workload"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batched_panda_{T}x{args.seeds}", "targets": T,
-                   "seeds_per_target": args.seeds, "dof": n, "link_spheres": int(rob.sphere_link.shape[0]),
-                   "obstacle_spheres": int(batch.scene.spheres.shape[0]), "top_k": k,
-                   "cd_sweeps": batch.params["cd_sweeps"], "polish_iters": batch.params["polish_iters"]},
-        "solved_targets": m["solved_targets"],
-        "success_rate": m["success_rate"],
-        "latency_ms": m["latency_ms"],
-        "stage_ms": m["stage_ms"],
-        "work_per_step": m["work_per_step"],
-        "roofline": dict(m["roofline"], traffic=measured_traffic()),
     }
-    def log(msg):
-        print(msg, file=sys.stderr, flush=True)
-
-    # the tiny configuration (8 targets x 64 seeds): the latency of one small solve
+    scene_note = ("obstacle centres uniform in the stated cube, rejected within 0.3 m of the base and in the "
+                  "column |c_xy| < 0.25 m, z < 0.55 m above it")
+    if not args.no_serve:
+        rates = [int(x) for x in args.serve_rates.split(",") if x]
+        if args.headline_rate not in rates:
+            rates.append(args.headline_rate)
+        sv = serving(H, ctx, torch, rates, args.serve_window, args.serve_warmup, args.serve_prefix,
+                     args.serve_slots, args.serve_chunk, log)
+        head = next(r for r in sv if r["rate_req_s"] == args.headline_rate)
+        line["value"] = head["served_window"]["solves_per_s"]
+        line["p50_latency_ms"] = head["served_window"]["p50_latency_ms"]
+        line["p99_latency_ms"] = head["served_window"]["p99_latency_ms"]
+        line["plain"] = head["plain_same_prefix"]
+        line["served_same_prefix"] = head["served_same_prefix"]
+        line["speedup_vs_plain"] = head["speedup_vs_plain"]
+        line["config"] = {"workload": f"serving_poisson_{args.headline_rate}_req_s_panda_1-16_targets_32-1024_seeds",
+                          "rate_req_s": args.headline_rate, "window_s": args.serve_window,
+                          "warmup_s": args.serve_warmup, "same_prefix_requests": head["same_prefix_requests"],
+                          "dof": rob.dof, "link_spheres": int(rob.sphere_link.shape[0]),
+                          "obstacle_spheres": int(batch.scene.spheres.shape[0]), "top_k": 1,
+                          "chunk_iters": args.serve_chunk, "max_slots": args.serve_slots,
+                          "cd_sweeps": 20, "polish_iters": 20, "scene": scene_note}
+        line["serving"] = sv
+    else:
+        line["value"] = m["value"]
+        line["config"] = {"workload": m["workload"], "scene": scene_note}
+    line["batched"] = dict(m, config={"targets": batch.T, "seeds_per_target": args.seeds, "dof": rob.dof,
+                                      "link_spheres": int(rob.sphere_link.shape[0]),
+                                      "obstacle_spheres": int(batch.scene.spheres.shape[0]),
+                                      "top_k": batch.params["top_k"], "cd_sweeps": batch.params["cd_sweeps"],
+                                      "polish_iters": batch.params["polish_iters"]})
     if not args.no_tiny:
         tb = W.config_tiny(host_seeds=False)
         mt = measure(H, ctx, torch, tb, 50, 5)
@@ -400,20 +598,26 @@ def main():
         log(f"tiny: {line['tiny']}")
     if not args.no_uneven:
         line["uneven"] = uneven(H, ctx, torch, 5, log)
-    if args.large:
+    if not args.no_large:
         lb = W.config_large()
         ml = measure(H, ctx, torch, lb, 3, 1)
-        line["large"] = dict({"workload": f"large_random20_{lb.T}x{int(lb.seed_offsets[1])}", "top_k": lb.params["top_k"],
-                              "cd_sweeps": lb.params["cd_sweeps"], "polish_iters": lb.params["polish_iters"]}, **ml)
+        line["large"] = dict({"workload": f"large_random20_{lb.T}x{int(lb.seed_offsets[1])}",
+                              "top_k": lb.params["top_k"], "cd_sweeps": lb.params["cd_sweeps"],
+                              "polish_iters": lb.params["polish_iters"], "obstacle_spheres": 128,
+                              "obstacle_boxes": 128, "scene": scene_note}, **ml)
         log(f"large: {line['large']}")
-    if not args.no_serve:
-        rates = [int(x) for x in args.serve_rates.split(",") if x]
-        line["serving"] = {"workload": "poisson_panda_1-16_targets_32-1024_seeds", "chunk_iters": args.serve_chunk,
-                           "max_slots": args.serve_slots, "duration_s": args.serve_duration,
-                           "rates": serving(H, ctx, torch, rates, args.serve_duration, args.serve_slots,
-                                            args.serve_chunk, args.plain_cap, log)}
+    if not args.no_dof:
+        line["dof_scaling"] = dof_scaling(H, ctx, torch, log)
+    if not args.no_tracking:
+        line["tracking"] = tracking(H, ctx, torch, log)
+    if not args.no_resample:
+        line["resampling"] = {"workload": m["workload"], "rows": resampling(H, ctx, torch, batch, log)}
+    per_unit = None
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(batch, min(args.cpu_targets, T))
+        cb, per_unit = cpu_baseline(batch, min(args.cpu_targets, batch.T), min(args.cpu_single_targets, batch.T))
+        line["cpu_baseline"] = cb
+        log(f"cpu baseline: {cb}")
+    line["roofline"] = roofline(m, per_unit, rob.dof)
     print(json.dumps(line), flush=True)
 
 

@@ -120,6 +120,9 @@ typedef struct {
     float succ_pos, succ_ori;/* success: collision free and |r_p| <= succ_pos, phi <= succ_ori */
     uint64_t rng_seed;       /* Philox key */
     int32_t collect_stats;   /* 1: time each kernel and count executed work (hjcd_get_stats) */
+    int32_t polish_variant;  /* launch shape of the PJ-IK kernel: 0 default, 1 the other occupancy
+                                (waves per SIMD 3 / 2 up to 8 joints, 2 / 1 up to 24, 1 / 2 above);
+                                the arithmetic is the same, so results are bit-identical */
 } hjcd_params;
 
 /* Per-call measurements of the last hjcd_solve / stage call made with
@@ -221,6 +224,34 @@ hjcd_status hjcd_select(hjcd_ctx ctx, int32_t T, const int64_t* seed_offsets /* 
                         const uint8_t* flag, float* q_out, float* err_p_out, float* err_o_out,
                         uint8_t* flag_out, int32_t* n_free, uint8_t* solved, void* stream);
 
+/* ---- tracking: targets along a path (Sec. V, hardware demonstration) -------
+ * The paper's demonstration tracks a moving pose in real time, keeping the
+ * returned solutions continuous.  Each pose of the path is solved from the
+ * solution set of the previous pose, and the returned solution is the one
+ * nearest the current configuration (readings: the paper gives no formula). */
+
+/* Warm-start seeds: q_prev [T*k][n_stride] (row-major, e.g. the q_out of the
+ * previous pose's hjcd_solve / hjcd_solve_near with top_k = k) -> q_out
+ * [n][T*M] (SoA, usable as hjcd_solve's seeds with M seeds per target).
+ * Seed m of target t starts at previous solution m mod k clipped to the
+ * limits; for m >= k it is also moved to clip(. + mu + sigma z), z drawn for
+ * seed index m at stage WARM (4) with the target's key. */
+hjcd_status hjcd_warm_seeds(hjcd_ctx ctx, hjcd_robot robot, int32_t T, int32_t k, int32_t n_stride,
+                            const float* q_prev, int32_t M, const uint32_t* target_keys,
+                            const hjcd_params* params, float* q_out, void* stream);
+
+/* hjcd_select with the nearest-solution order: per target, seeds that are
+ * collision free with err_p <= succ_pos and err_o <= succ_ori come first,
+ * ordered by squared joint distance to q_ref [T][n_stride] (device, row t =
+ * target t's current configuration); then the other collision-free seeds and
+ * then the colliding ones, each by cost; ties -> lower index.  n_free and
+ * solved as hjcd_select. */
+hjcd_status hjcd_select_near(hjcd_ctx ctx, int32_t T, const int64_t* seed_offsets /* host */, int32_t n,
+                             int32_t n_stride, const hjcd_params* params, const float* q, const float* cost,
+                             const float* err_p, const float* err_o, const uint8_t* flag, const float* q_ref,
+                             float* q_out, float* err_p_out, float* err_o_out, uint8_t* flag_out,
+                             int32_t* n_free, uint8_t* solved, void* stream);
+
 /* ---- the whole batched solve (Alg. HJCD-IK) --------------------------------
  * T targets, each solved with the robot robots[robot_of_target[t]] (host,
  * NULL = robots[0]) from its seeds: seeds [n_max][S] (device, rows beyond a
@@ -233,6 +264,15 @@ hjcd_status hjcd_solve(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots,
                        const int64_t* seed_offsets /* host [T+1] */, const uint32_t* target_keys,
                        const float* seeds, const hjcd_params* params, float* q_out, float* err_p,
                        float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream);
+
+/* hjcd_solve whose final selection is hjcd_select_near's order around
+ * q_ref [T][n_max] (device): the tracking form of the whole solve. */
+hjcd_status hjcd_solve_near(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots, hjcd_scene scene, int32_t T,
+                            const int32_t* robot_of_target /* host */, const float* targets,
+                            const int64_t* seed_offsets /* host [T+1] */, const uint32_t* target_keys,
+                            const float* seeds, const hjcd_params* params, const float* q_ref, float* q_out,
+                            float* err_p, float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved,
+                            void* stream);
 
 /* Measurements of the last call made with collect_stats = 1 (synchronises
  * the stream that call used). */
@@ -247,8 +287,11 @@ hjcd_status hjcd_get_stats(hjcd_ctx ctx, hjcd_stats* out);
  * kept), and captures the whole solve into one hipGraph: the robots' solve
  * and collision kernels on concurrent branches, then the selection.
  * hjcd_plan_execute replays that graph on a stream: one launch for the whole
- * uneven batch.  The results equal hjcd_solve's on the same inputs.  Plans
- * do not resample (resample_K must be 0) and collect no statistics.  The
+ * uneven batch.  The results equal hjcd_solve's on the same inputs, bit for
+ * bit (the tuner chooses launch shapes only).  With resample_K > 0 each
+ * robot's branch ranks its targets' CD seeds and polishes the replicated
+ * ones (Alg. HJCD-IK) before its collision test.  Plans collect no
+ * statistics.  The
  * caller keeps the buffers alive and unchanged in size until
  * hjcd_plan_destroy; their contents may change between executions. */
 typedef struct hjcd_plan_s* hjcd_plan;

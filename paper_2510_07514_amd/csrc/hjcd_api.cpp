@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,8 +62,12 @@ hjcd_status ensure(hjcd_ctx c, DevBuf& b, size_t bytes) {
 struct Staging {
     hjcd_ctx c;
     hipStream_t st;
+    bool may_grow = true;  // false: the buffer the context was created with must do
     hjcd_status begin(size_t total) {
         HIP_TRY(hipEventSynchronize(c->staging_ev));
+        if (c->pinned_cap < total && !may_grow)
+            return fail(HJCD_E_INVALID, "%zu bytes of layout exceed the context's %zu-byte staging buffer", total,
+                        c->pinned_cap);
         if (c->pinned_cap < total) {
             if (c->pinned) HIP_TRY(hipHostFree(c->pinned));
             c->pinned = nullptr;
@@ -98,6 +103,12 @@ size_t staging_bytes(std::initializer_list<size_t> parts) {
 
 bool finite_f(float x) { return std::isfinite(x); }
 
+// Pinned staging bytes of a solve's layout upload for T targets.
+size_t layout_staging_bytes(int32_t T) {
+    return staging_bytes({sizeof(int64_t) * (T + 1), sizeof(int64_t) * (T + 1), sizeof(int32_t) * (size_t)T,
+                          sizeof(int64_t) * (T + 1)});
+}
+
 }  // namespace
 
 hjcd_status hjcd::check_params(const hjcd_params* p) {
@@ -121,6 +132,7 @@ hjcd_status hjcd::check_params(const hjcd_params* p) {
         return fail(HJCD_E_INVALID, "top_k must be in [1, %d]", HJCD_MAX_TOPK);
     if (p->resample_K < 0 || (p->resample_K > 0 && p->resample_B < p->resample_K))
         return fail(HJCD_E_INVALID, "resample needs K >= 0 and B >= K");
+    if (p->polish_variant != 0 && p->polish_variant != 1) return fail(HJCD_E_INVALID, "polish_variant must be 0 or 1");
     return HJCD_OK;
 }
 
@@ -283,6 +295,7 @@ void hjcd_params_default(hjcd_params* p) {
     p->succ_ori = (float)(3.14159265358979323846 / 180.0);
     p->rng_seed = 0;
     p->collect_stats = 0;
+    p->polish_variant = 0;
 }
 
 hjcd_status hjcd_ctx_create(int device, hjcd_ctx* out) {
@@ -636,6 +649,7 @@ static hjcd_status stage_common(hjcd_ctx c, hjcd_robot r, int32_t T, const float
     a.do_polish = cd ? 0 : 1;
     a.kp = kparams(*p);
     a.counters = ss.counters();
+    a.variant = p->polish_variant;
     HIP_TRY(launch_solve(a, st));
     if ((s = ss.mark(cd ? SS_CD : SS_POLISH)) != HJCD_OK) return s;
     ss.end();
@@ -705,10 +719,11 @@ hjcd_status hjcd_resample(hjcd_ctx c, hjcd_robot r, int32_t T, const int64_t* of
     return HJCD_OK;
 }
 
-hjcd_status hjcd_select(hjcd_ctx c, int32_t T, const int64_t* offs, int32_t n, int32_t n_stride,
-                        const hjcd_params* p, const float* q, const float* cost, const float* ep, const float* eo,
-                        const uint8_t* flag, float* q_out, float* ep_out, float* eo_out, uint8_t* fl_out,
-                        int32_t* n_free, uint8_t* solved, void* stream) {
+static hjcd_status select_common(hjcd_ctx c, int32_t T, const int64_t* offs, int32_t n, int32_t n_stride,
+                                 const hjcd_params* p, const float* q, const float* cost, const float* ep,
+                                 const float* eo, const uint8_t* flag, const float* q_ref, float* q_out,
+                                 float* ep_out, float* eo_out, uint8_t* fl_out, int32_t* n_free, uint8_t* solved,
+                                 void* stream) {
     hjcd_status s;
     if ((s = check_params(p)) != HJCD_OK) return s;
     if ((s = check_offsets(T, offs)) != HJCD_OK) return s;
@@ -744,16 +759,53 @@ hjcd_status hjcd_select(hjcd_ctx c, int32_t T, const int64_t* offs, int32_t n, i
     a.fl_out = fl_out;
     a.n_free = n_free;
     a.solved = solved;
+    a.q_ref = q_ref;
     HIP_TRY(launch_select(a, st));
+    return HJCD_OK;
+}
+
+hjcd_status hjcd_select(hjcd_ctx c, int32_t T, const int64_t* offs, int32_t n, int32_t n_stride,
+                        const hjcd_params* p, const float* q, const float* cost, const float* ep, const float* eo,
+                        const uint8_t* flag, float* q_out, float* ep_out, float* eo_out, uint8_t* fl_out,
+                        int32_t* n_free, uint8_t* solved, void* stream) {
+    return select_common(c, T, offs, n, n_stride, p, q, cost, ep, eo, flag, nullptr, q_out, ep_out, eo_out, fl_out,
+                         n_free, solved, stream);
+}
+
+hjcd_status hjcd_select_near(hjcd_ctx c, int32_t T, const int64_t* offs, int32_t n, int32_t n_stride,
+                             const hjcd_params* p, const float* q, const float* cost, const float* ep,
+                             const float* eo, const uint8_t* flag, const float* q_ref, float* q_out, float* ep_out,
+                             float* eo_out, uint8_t* fl_out, int32_t* n_free, uint8_t* solved, void* stream) {
+    if (T > 0 && !q_ref) return fail(HJCD_E_INVALID, "q_ref is required");
+    return select_common(c, T, offs, n, n_stride, p, q, cost, ep, eo, flag, q_ref, q_out, ep_out, eo_out, fl_out,
+                         n_free, solved, stream);
+}
+
+hjcd_status hjcd_warm_seeds(hjcd_ctx c, hjcd_robot r, int32_t T, int32_t k, int32_t n_stride, const float* q_prev,
+                            int32_t M, const uint32_t* tkeys, const hjcd_params* p, float* q_out, void* stream) {
+    hjcd_status s;
+    if ((s = check_params(p)) != HJCD_OK) return s;
+    if (T < 0 || k < 1 || M < 0) return fail(HJCD_E_INVALID, "need T >= 0, k >= 1, M >= 0");
+    if ((s = check_ctx(c)) != HJCD_OK) return s;
+    if ((s = check_robot(c, r)) != HJCD_OK) return s;
+    if (n_stride < r->n || n_stride > HJCD_MAX_DOF)
+        return fail(HJCD_E_INVALID, "n_stride must be in [dof, %d]", HJCD_MAX_DOF);
+    if ((int64_t)T * M == 0) return HJCD_OK;
+    if (!q_prev || !q_out) return fail(HJCD_E_INVALID, "q_prev and q_out are required");
+    if ((s = bind(c)) != HJCD_OK) return s;
+    HIP_TRY(launch_warm(r->dev, r->n, T, k, n_stride, q_prev, M, tkeys, p->rng_seed, p->mu, p->sigma, q_out,
+                        (hipStream_t)stream));
     return HJCD_OK;
 }
 
 // ---- the whole solve --------------------------------------------------------
 
-hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
-                       const int32_t* robot_of_target, const float* targets, const int64_t* offs,
-                       const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out, float* ep,
-                       float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream) {
+// The whole solve.  Work arrays come from the context (grown on demand).
+static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
+                              const int32_t* robot_of_target, const float* targets, const int64_t* offs,
+                              const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out,
+                              float* ep, float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream,
+                              const float* q_ref = nullptr) {
     hjcd_status s;
     if (n_robots < 1 || n_robots > HJCD_MAX_ROBOTS || !robots)
         return fail(HJCD_E_INVALID, "need 1..%d robots", HJCD_MAX_ROBOTS);
@@ -796,43 +848,56 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
         for (int32_t b = 0; b <= T; ++b) voffs2[b] = (int64_t)b * Bp;
     }
 
+    // work arrays
+    const int64_t Sf = resample ? S2 : S;  // slots of the final stage
+    const size_t sz_voffs = sizeof(int64_t) * (T + 1), sz_perm = sizeof(int32_t) * (size_t)T;
+    const size_t sz_qw = sizeof(float) * (size_t)n_max * std::max<int64_t>(S, 1);
+    const size_t sz_qw2 = resample ? sizeof(float) * (size_t)n_max * std::max<int64_t>(S2, 1) : 0;
+    const size_t sz_f = sizeof(float) * std::max<int64_t>(Sf, 1);
+    const size_t sz_cost = sizeof(float) * std::max<int64_t>(std::max(S, Sf), 1);
+    const size_t sz_flag = std::max<int64_t>(Sf, 1);
+    const size_t sz_rank = resample ? sizeof(int32_t) * (size_t)T * K : 0;
+    void *w_voffs, *w_voffs2, *w_perm, *w_coffs, *w_qw, *w_qw2, *w_ep, *w_eo, *w_cost, *w_flag, *w_rank;
+    if ((s = ensure(c, c->voffs, sz_voffs)) != HJCD_OK || (s = ensure(c, c->voffs2, sz_voffs)) != HJCD_OK ||
+        (s = ensure(c, c->tperm, sz_perm)) != HJCD_OK || (s = ensure(c, c->coffs, sz_voffs)) != HJCD_OK ||
+        (s = ensure(c, c->q_work, sz_qw)) != HJCD_OK ||
+        (resample && (s = ensure(c, c->q_work2, sz_qw2)) != HJCD_OK) ||
+        (s = ensure(c, c->ep, sz_f)) != HJCD_OK || (s = ensure(c, c->eo, sz_f)) != HJCD_OK ||
+        (s = ensure(c, c->cost, sz_cost)) != HJCD_OK || (s = ensure(c, c->flag, sz_flag)) != HJCD_OK ||
+        (resample && (s = ensure(c, c->rank, sz_rank)) != HJCD_OK))
+        return s;
+    w_voffs = c->voffs.p;
+    w_voffs2 = c->voffs2.p;
+    w_perm = c->tperm.p;
+    w_coffs = c->coffs.p;
+    w_qw = c->q_work.p;
+    w_qw2 = c->q_work2.p;
+    w_ep = c->ep.p;
+    w_eo = c->eo.p;
+    w_cost = c->cost.p;
+    w_flag = c->flag.p;
+    w_rank = c->rank.p;
     StatScope ss{c, st, false};
     if ((s = ss.begin(p->collect_stats != 0, S)) != HJCD_OK) return s;
-    if ((s = ensure(c, c->voffs, sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->voffs2, sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->tperm, sizeof(int32_t) * T)) != HJCD_OK) return s;
-    if ((s = ensure(c, c->coffs, sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->q_work, sizeof(float) * (size_t)n_max * std::max<int64_t>(S, 1))) != HJCD_OK) return s;
-    const int64_t Sf = resample ? S2 : S;  // slots of the final stage
-    if (resample &&
-        (s = ensure(c, c->q_work2, sizeof(float) * (size_t)n_max * std::max<int64_t>(S2, 1))) != HJCD_OK)
-        return s;
-    if ((s = ensure(c, c->ep, sizeof(float) * std::max<int64_t>(Sf, 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->eo, sizeof(float) * std::max<int64_t>(Sf, 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->cost, sizeof(float) * std::max<int64_t>(std::max(S, Sf), 1))) != HJCD_OK) return s;
-    if ((s = ensure(c, c->flag, std::max<int64_t>(Sf, 1))) != HJCD_OK) return s;
-    if (resample && (s = ensure(c, c->rank, sizeof(int32_t) * (size_t)T * K)) != HJCD_OK) return s;
     {
         Staging sg{c, st};
-        if ((s = sg.begin(staging_bytes({sizeof(int64_t) * (T + 1), sizeof(int64_t) * (T + 1),
-                                         sizeof(int32_t) * (size_t)T, sizeof(int64_t) * (T + 1)}))) != HJCD_OK)
-            return s;
-        if ((s = sg.put(c->voffs.p, voffs.data(), sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
-        if (resample && (s = sg.put(c->voffs2.p, voffs2.data(), sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
-        if (!identity && (s = sg.put(c->tperm.p, perm.data(), sizeof(int32_t) * T)) != HJCD_OK) return s;
+        if ((s = sg.begin(layout_staging_bytes(T))) != HJCD_OK) return s;
+        if ((s = sg.put(w_voffs, voffs.data(), sz_voffs)) != HJCD_OK) return s;
+        if (resample && (s = sg.put(w_voffs2, voffs2.data(), sz_voffs)) != HJCD_OK) return s;
+        if (!identity && (s = sg.put(w_perm, perm.data(), sz_perm)) != HJCD_OK) return s;
         // caller offsets, for gathering the caller's seeds into the grouped layout
-        if (!identity && seeds && (s = sg.put(c->coffs.p, offs, sizeof(int64_t) * (T + 1))) != HJCD_OK) return s;
+        if (!identity && seeds && (s = sg.put(w_coffs, offs, sz_voffs)) != HJCD_OK) return s;
         if ((s = sg.end()) != HJCD_OK) return s;
     }
-    const int64_t* d_voffs = (const int64_t*)c->voffs.p;
-    const int64_t* d_voffs2 = (const int64_t*)c->voffs2.p;
-    const int32_t* d_perm = identity ? nullptr : (const int32_t*)c->tperm.p;
-    float* qw = (float*)c->q_work.p;
+    const int64_t* d_voffs = (const int64_t*)w_voffs;
+    const int64_t* d_voffs2 = (const int64_t*)w_voffs2;
+    const int32_t* d_perm = identity ? nullptr : (const int32_t*)w_perm;
+    float* qw = (float*)w_qw;
     const float* q_src = seeds;
     int64_t q_src_stride = S;
     if (seeds && !identity) {
         // grouped copy of the caller's seeds
-        HIP_TRY(launch_gather(n_max, T, (const int64_t*)c->coffs.p, d_voffs, d_perm, S, S, seeds, qw, st));
+        HIP_TRY(launch_gather(n_max, T, (const int64_t*)w_coffs, d_voffs, d_perm, S, S, seeds, qw, st));
         q_src = qw;
     }
     const KernelParams kp = kparams(*p);
@@ -869,15 +934,16 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
             a.q_in = cd ? q_src : qw;
             a.q_in_stride = cd ? q_src_stride : S;
             a.q_out = qw;
-            a.err_p = (float*)c->ep.p;
-            a.err_o = (float*)c->eo.p;
-            a.cost = (float*)c->cost.p;
+            a.err_p = (float*)w_ep;
+            a.err_o = (float*)w_eo;
+            a.cost = (float*)w_cost;
             a.traj = nullptr;
             a.init_mode = cd ? (seeds ? INIT_LOAD : INIT_UNIFORM) : INIT_LOAD;
             a.do_cd = cd ? 1 : 0;
             a.do_polish = cd ? 0 : 1;
             a.kp = kp;
             a.counters = ss.counters();
+            a.variant = p->polish_variant;
             return a;
         };
         for (int ri = 0; ri < n_robots; ++ri) {
@@ -903,7 +969,7 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
             a.q_in = q_src;
             a.q_in_stride = q_src_stride;
             a.q_out = qw;
-            a.cost = (float*)c->cost.p;
+            a.cost = (float*)w_cost;
             a.init_mode = seeds ? INIT_LOAD : INIT_UNIFORM;
             a.do_cd = 1;
             a.do_polish = 0;
@@ -912,11 +978,11 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
             HIP_TRY(launch_solve(a, st));
         }
         if ((s = ss.mark(SS_CD)) != HJCD_OK) return s;
-        HIP_TRY(launch_rank(T, d_voffs, (const float*)c->cost.p, K, (int32_t*)c->rank.p, st));
-        float* qw2 = (float*)c->q_work2.p;
+        HIP_TRY(launch_rank(T, d_voffs, (const float*)w_cost, K, (int32_t*)w_rank, st));
+        float* qw2 = (float*)w_qw2;
         for (int ri = 0; ri < n_robots; ++ri) {
             HIP_TRY(launch_replicate(robots[ri]->dev, robots[ri]->n, rb_tb[ri], rb_tb[ri + 1], T, d_voffs, d_perm, S,
-                                     qw, (const int32_t*)c->rank.p, K, Bp, tkeys, p->rng_seed, p->mu, p->sigma,
+                                     qw, (const int32_t*)w_rank, K, Bp, tkeys, p->rng_seed, p->mu, p->sigma,
                                      qw2, st));
         }
         if ((s = ss.mark(SS_RESAMPLE)) != HJCD_OK) return s;
@@ -932,19 +998,20 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
             a.q_in = qw2;
             a.q_in_stride = S2;
             a.q_out = qw2;
-            a.err_p = (float*)c->ep.p;
-            a.err_o = (float*)c->eo.p;
-            a.cost = (float*)c->cost.p;
+            a.err_p = (float*)w_ep;
+            a.err_o = (float*)w_eo;
+            a.cost = (float*)w_cost;
             a.init_mode = INIT_LOAD;
             a.do_cd = 0;
             a.do_polish = 1;
             a.kp = kp;
             a.counters = ss.counters();
+            a.variant = p->polish_variant;
             HIP_TRY(launch_solve(a, st));
         }
         if ((s = ss.mark(SS_POLISH)) != HJCD_OK) return s;
     }
-    const float* qf = resample ? (const float*)c->q_work2.p : qw;
+    const float* qf = resample ? (const float*)w_qw2 : qw;
     const int64_t* d_vf = resample ? d_voffs2 : d_voffs;
     for (int ri = 0; ri < n_robots; ++ri) {
         const int32_t tb = rb_tb[ri], te = rb_tb[ri + 1];
@@ -961,7 +1028,7 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
         a.n_osph = sc ? sc->n_sph : 0;
         a.obox = sc ? sc->box : nullptr;
         a.n_obox = sc ? sc->n_box : 0;
-        a.flag = (uint8_t*)c->flag.p + base;
+        a.flag = (uint8_t*)w_flag + base;
         a.counters = ss.counters();
         HIP_TRY(launch_collide(a, st));
     }
@@ -974,10 +1041,10 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
     a.n_stride = n_max;
     a.S = Sf;
     a.q = qf;
-    a.cost = (const float*)c->cost.p;
-    a.err_p = (const float*)c->ep.p;
-    a.err_o = (const float*)c->eo.p;
-    a.flag = (const uint8_t*)c->flag.p;
+    a.cost = (const float*)w_cost;
+    a.err_p = (const float*)w_ep;
+    a.err_o = (const float*)w_eo;
+    a.flag = (const uint8_t*)w_flag;
     a.k = p->top_k;
     a.succ_pos = p->succ_pos;
     a.succ_ori = p->succ_ori;
@@ -987,10 +1054,29 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
     a.fl_out = flag;
     a.n_free = n_free;
     a.solved = solved;
+    a.q_ref = q_ref;
     HIP_TRY(launch_select(a, st));
     if ((s = ss.mark(SS_SELECT)) != HJCD_OK) return s;
     ss.end();
     return HJCD_OK;
+}
+
+hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
+                       const int32_t* robot_of_target, const float* targets, const int64_t* offs,
+                       const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out, float* ep,
+                       float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream) {
+    return solve_impl(c, n_robots, robots, sc, T, robot_of_target, targets, offs, tkeys, seeds, p, q_out, ep, eo, flag,
+                      n_free, solved, stream);
+}
+
+hjcd_status hjcd_solve_near(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
+                            const int32_t* robot_of_target, const float* targets, const int64_t* offs,
+                            const uint32_t* tkeys, const float* seeds, const hjcd_params* p, const float* q_ref,
+                            float* q_out, float* ep, float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved,
+                            void* stream) {
+    if (T > 0 && !q_ref) return fail(HJCD_E_INVALID, "q_ref is required");
+    return solve_impl(c, n_robots, robots, sc, T, robot_of_target, targets, offs, tkeys, seeds, p, q_out, ep, eo, flag,
+                      n_free, solved, stream, q_ref);
 }
 
 hjcd_status hjcd_get_stats(hjcd_ctx c, hjcd_stats* out) {

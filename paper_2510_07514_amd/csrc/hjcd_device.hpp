@@ -308,7 +308,7 @@ __device__ __forceinline__ U4 philox(U4 ctr, uint32_t k0, uint32_t k1) {
     return ctr;
 }
 
-enum { STAGE_INIT = 0, STAGE_CD = 1, STAGE_RESAMPLE = 2, STAGE_POLISH = 3 };
+enum { STAGE_INIT = 0, STAGE_CD = 1, STAGE_RESAMPLE = 2, STAGE_POLISH = 3, STAGE_WARM = 4 };
 
 // Uniform in (0, 1) from the top 24 bits: exact in single precision.
 __device__ __forceinline__ float uni24(uint32_t x) {

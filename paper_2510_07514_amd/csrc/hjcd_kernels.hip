@@ -377,7 +377,18 @@ __device__ __forceinline__ uint64_t cost_key(float c, uint32_t m) {
     return ((uint64_t)b << 32) | m;
 }
 
-// Final selection (Alg. HJCD-IK, last line): order (flag != 0, cost, index).
+// Key of the nearest-solution order: class (0: collision free within the
+// success tolerances, 1: other collision-free seeds, 2: colliding) in bits
+// 62-63, then the squared joint distance to the reference (class 0) or the
+// cost (>= 0, sign bit dropped) in bits 31-61, then the seed index.
+__device__ __forceinline__ uint64_t near_key(uint32_t cls, float v, uint32_t m) {
+    const uint32_t b = __float_as_uint(v) & 0x7FFFFFFFu;
+    return ((uint64_t)cls << 62) | ((uint64_t)b << 31) | (uint64_t)(m & 0x7FFFFFFFu);
+}
+
+// Final selection (Alg. HJCD-IK, last line): order (flag != 0, cost, index);
+// with a reference configuration per target (a.q_ref), the tracking order of
+// near_key.
 __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
     const int b = blockIdx.x;
     const int t = a.tperm ? a.tperm[b] : b;
@@ -392,8 +403,23 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
     for (int r = 0; r < a.k; ++r) {
         uint64_t best = ~0ull;
         for (int64_t m = lane; m < M; m += 64) {
-            const uint64_t key = ((uint64_t)(a.flag[b0 + m] != 0) << 63) |
-                                 cost_key(a.cost[b0 + m], (uint32_t)m);
+            const int64_t sm = b0 + m;
+            uint64_t key;
+            if (a.q_ref) {
+                const bool fr = a.flag[sm] == 0;
+                const bool good = fr && a.err_p[sm] <= a.succ_pos && a.err_o[sm] <= a.succ_ori;
+                float v = a.cost[sm];
+                if (good) {
+                    v = 0.f;
+                    for (int j = 0; j < a.n; ++j) {
+                        const float d = a.q[(int64_t)j * a.S + sm] - a.q_ref[(int64_t)t * a.n_stride + j];
+                        v = fmaf(d, d, v);
+                    }
+                }
+                key = near_key(good ? 0u : (fr ? 1u : 2u), v, (uint32_t)m);
+            } else {
+                key = ((uint64_t)(a.flag[sm] != 0) << 63) | cost_key(a.cost[sm], (uint32_t)m);
+            }
             if ((r == 0 || key > prev) && key < best) best = key;
         }
         best = wave_min_u64(best);
@@ -408,7 +434,7 @@ __global__ __launch_bounds__(64) void k_select(SelectArgs a) {
             continue;
         }
         prev = best;
-        const int64_t s = b0 + (int64_t)(uint32_t)best;
+        const int64_t s = b0 + (int64_t)(a.q_ref ? (uint32_t)(best & 0x7FFFFFFFull) : (uint32_t)best);
         if (lane < a.n_stride) a.q_out[o * a.n_stride + lane] = lane < a.n ? a.q[(int64_t)lane * a.S + s] : 0.f;
         const float ep = a.err_p[s], eo = a.err_o[s];
         const uint8_t fl = a.flag[s];
@@ -474,6 +500,31 @@ __global__ __launch_bounds__(256) void k_replicate(const DevRobot* __restrict__ 
 #pragma unroll
     for (int i = 0; i < NM; ++i)
         if (i < n) q_out[(int64_t)i * Sout + v] = th[i];
+}
+
+// Warm start on a path: seed m of target t starts at previous solution
+// m mod k (row t*k + m%k of q_prev [T*k][n_stride]), clipped to the limits,
+// and for m >= k moved by clip(. + mu + sigma z), z drawn for seed index m at
+// stage WARM.  q_out [n][T*M].
+template <int NM>
+__global__ __launch_bounds__(256) void k_warm(const DevRobot* __restrict__ rb, int n, int32_t T, int32_t k,
+                                              int32_t n_stride, const float* __restrict__ q_prev, int32_t M,
+                                              const uint32_t* __restrict__ tkeys, uint64_t seed, float mu,
+                                              float sigma, float* __restrict__ q_out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t S = (int64_t)T * M;
+    if (v >= S) return;
+    const int32_t t = (int32_t)(v / M);
+    const int32_t m = (int32_t)(v % M);
+    const int64_t src = ((int64_t)t * k + m % k) * n_stride;
+    float th[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) th[i] = i < n ? clampf(q_prev[src + i], rb->lo[i], rb->hi[i]) : 0.f;
+    if (m >= k)
+        perturb<NM>(rb, n, th, seed, (uint32_t)m, tkeys ? tkeys[t] : (uint32_t)t, STAGE_WARM, 0, mu, sigma);
+#pragma unroll
+    for (int i = 0; i < NM; ++i)
+        if (i < n) q_out[(int64_t)i * S + v] = th[i];
 }
 
 // Caller layout -> robot-grouped layout.
@@ -627,6 +678,20 @@ hipError_t launch_replicate(const DevRobot* rb, int n, int32_t tb, int32_t te, i
                        S_in, q_in, rank, K, Bp, tkeys, seed, mu, sigma, q_out, Sout)
     HJCD_DISPATCH_NM(n, L_REP);
 #undef L_REP
+    return hipGetLastError();
+}
+
+hipError_t launch_warm(const DevRobot* rb, int n, int32_t T, int32_t k, int32_t n_stride, const float* q_prev,
+                       int32_t M, const uint32_t* tkeys, uint64_t seed, float mu, float sigma, float* q_out,
+                       hipStream_t st) {
+    const int64_t S = (int64_t)T * M;
+    if (S <= 0) return hipSuccess;
+    const unsigned nb = blocks_for(S, 256);
+#define L_WARM(NMV)                                                                                       \
+    hipLaunchKernelGGL(k_warm<NMV>, dim3(nb), dim3(256), 0, st, rb, n, T, k, n_stride, q_prev, M, tkeys, \
+                       seed, mu, sigma, q_out)
+    HJCD_DISPATCH_NM(n, L_WARM);
+#undef L_WARM
     return hipGetLastError();
 }
 

@@ -107,9 +107,15 @@ struct SelectArgs {
     uint8_t* fl_out;
     int32_t* n_free;
     uint8_t* solved;
+    const float* q_ref;      // [T][n_stride] by target id, or nullptr (cost order)
 };
 
 hipError_t launch_select(const SelectArgs& a, hipStream_t st);
+
+// Warm start for targets on a path: q_out [n][T*M] from q_prev [T*k][n_stride].
+hipError_t launch_warm(const DevRobot* rb, int n, int32_t T, int32_t k, int32_t n_stride, const float* q_prev,
+                       int32_t M, const uint32_t* tkeys, uint64_t seed, float mu, float sigma, float* q_out,
+                       hipStream_t st);
 
 // Mid top-K ranking over permuted targets: rank [T][K] = seed indices
 // (within target) of the K smallest (cost, index); rank r >= M repeats rank

@@ -42,6 +42,17 @@ struct hjcd_plan_s {
     float* eo = nullptr;
     float* cost = nullptr;
     uint8_t* fl = nullptr;
+    // top-K and replication between the stages (resample_K > 0): per target
+    // B' = floor(B/K) K polished slots at t B' (grouped order), their own
+    // joint, cost and offset arrays (a robot's branch ranks its CD costs
+    // while another branch polishes, so the two stages never share one)
+    bool resample = false;
+    int32_t K = 0, Bp = 0;
+    int64_t S2 = 0;
+    int64_t* d_voffs2 = nullptr;
+    int32_t* rank = nullptr;
+    float* qw2 = nullptr;
+    float* cost2 = nullptr;
     hjcd_tune_choice choice[HJCD_MAX_ROBOTS] = {};
     hipStream_t main = nullptr;
     hipStream_t side[HJCD_MAX_ROBOTS] = {};
@@ -63,7 +74,8 @@ hjcd_status dalloc(T** p, size_t count) {
 void plan_free(hjcd_plan p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void* bufs[] = {p->d_voffs, p->d_coffs, p->d_perm, p->qw, p->ep, p->eo, p->cost, p->fl};
+    void* bufs[] = {p->d_voffs, p->d_coffs, p->d_perm, p->qw, p->ep, p->eo, p->cost, p->fl,
+                    p->d_voffs2, p->rank, p->qw2, p->cost2};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < HJCD_MAX_ROBOTS; ++i) {
@@ -99,6 +111,23 @@ SolveArgs solve_args(hjcd_plan p, int ri, int stage) {
     a.err_p = p->ep;
     a.err_o = p->eo;
     a.cost = p->cost;
+    if (stage == 0 && p->resample) {
+        // only the CD costs are read (by the ranking); the error arrays hold
+        // the polished slots, which another robot's branch may be writing
+        a.err_p = nullptr;
+        a.err_o = nullptr;
+    }
+    if (stage == 1 && p->resample) {
+        // PJ-IK on the replicated slots of this robot's targets
+        a.map.voffs = p->d_voffs2;
+        a.map.base = (int64_t)m.tb * p->Bp;
+        a.map.Sv = (int64_t)(m.te - m.tb) * p->Bp;
+        a.S = p->S2;
+        a.q_in = p->qw2;
+        a.q_in_stride = p->S2;
+        a.q_out = p->qw2;
+        a.cost = p->cost2;
+    }
     a.traj = nullptr;
     a.init_mode = (stage == 1 || p->seeds) ? INIT_LOAD : INIT_UNIFORM;
     a.do_cd = stage == 0;
@@ -111,13 +140,14 @@ SolveArgs solve_args(hjcd_plan p, int ri, int stage) {
 }
 
 CollideArgs collide_args(hjcd_plan p, int ri) {
-    const int64_t base = p->grp.voffs[p->grp.rb_tb[ri]];
+    const int32_t tb = p->grp.rb_tb[ri], te = p->grp.rb_tb[ri + 1];
+    const int64_t base = p->resample ? (int64_t)tb * p->Bp : p->grp.voffs[tb];
     CollideArgs a{};
     a.rb = p->robots[ri]->dev;
     a.n = p->robots[ri]->n;
-    a.S = p->grp.voffs[p->grp.rb_tb[ri + 1]] - base;
-    a.q = p->qw + base;
-    a.q_stride = p->S;
+    a.S = p->resample ? (int64_t)(te - tb) * p->Bp : p->grp.voffs[te] - base;
+    a.q = (p->resample ? p->qw2 : p->qw) + base;
+    a.q_stride = p->resample ? p->S2 : p->S;
     a.osph = p->scene ? p->scene->sph : nullptr;
     a.n_osph = p->scene ? p->scene->n_sph : 0;
     a.obox = p->scene ? p->scene->box : nullptr;
@@ -125,6 +155,17 @@ CollideArgs collide_args(hjcd_plan p, int ri) {
     a.flag = p->fl + base;
     a.counters = nullptr;
     return a;
+}
+
+// Top-K ranking of robot ri's targets by their CD costs and the noisy
+// replication of the K best into the polished slots (Alg. HJCD-IK).
+hipError_t launch_between(hjcd_plan p, int ri, hipStream_t st) {
+    const int32_t tb = p->grp.rb_tb[ri], te = p->grp.rb_tb[ri + 1];
+    hipError_t e = launch_rank(te - tb, p->d_voffs + tb, p->cost, p->K, p->rank + (int64_t)tb * p->K, st);
+    if (e != hipSuccess) return e;
+    return launch_replicate(p->robots[ri]->dev, p->robots[ri]->n, tb, te, p->T, p->d_voffs,
+                            p->grp.identity ? nullptr : p->d_perm, p->S, p->qw, p->rank, p->K, p->Bp, p->tkeys,
+                            p->params.rng_seed, p->params.mu, p->params.sigma, p->qw2, st);
 }
 
 // The whole solve on `st`: per robot, solve then collision on a branch of
@@ -137,6 +178,7 @@ hjcd_status enqueue(hjcd_plan p, hipStream_t st) {
         if (p->choice[ri].seeds == 0) continue;
         HIP_TRY(hipStreamWaitEvent(p->side[ri], p->fork, 0));
         HIP_TRY(launch_solve(solve_args(p, ri, 0), p->side[ri]));
+        if (p->resample) HIP_TRY(launch_between(p, ri, p->side[ri]));
         HIP_TRY(launch_solve(solve_args(p, ri, 1), p->side[ri]));
         HIP_TRY(launch_collide(collide_args(p, ri), p->side[ri]));
         HIP_TRY(hipEventRecord(p->join[ri], p->side[ri]));
@@ -144,13 +186,13 @@ hjcd_status enqueue(hjcd_plan p, hipStream_t st) {
     }
     SelectArgs a{};
     a.T = p->T;
-    a.offsets = p->d_voffs;
+    a.offsets = p->resample ? p->d_voffs2 : p->d_voffs;
     a.tperm = p->grp.identity ? nullptr : p->d_perm;
     a.n = p->n_max;
     a.n_stride = p->n_max;
-    a.S = p->S;
-    a.q = p->qw;
-    a.cost = p->cost;
+    a.S = p->resample ? p->S2 : p->S;
+    a.q = p->resample ? p->qw2 : p->qw;
+    a.cost = p->resample ? p->cost2 : p->cost;
     a.err_p = p->ep;
     a.err_o = p->eo;
     a.flag = p->fl;
@@ -180,6 +222,7 @@ hjcd_status autotune(hjcd_plan p, int ri, float* qs) {
     // PO-CCD once; every timed PJ-IK launch then polishes the same CD
     // results (read from qw) into the scratch rows `qs`
     HIP_TRY(launch_solve(solve_args(p, ri, 0), p->main));
+    if (p->resample) HIP_TRY(launch_between(p, ri, p->main));
     for (int v = 0; v < 2; ++v) {
         for (int bt : kBlocks) {
             p->choice[ri].variant = v;
@@ -221,9 +264,11 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
     if (n_robots < 1 || n_robots > HJCD_MAX_ROBOTS || !robots)
         return fail(HJCD_E_INVALID, "need 1..%d robots", HJCD_MAX_ROBOTS);
     if ((s = check_params(params)) != HJCD_OK) return s;
-    if (params->resample_K > 0) return fail(HJCD_E_UNSUPPORTED, "plans do not resample (resample_K must be 0)");
     if ((s = check_offsets(T, offs)) != HJCD_OK) return s;
     if (T < 1) return fail(HJCD_E_INVALID, "a plan needs T >= 1");
+    if (params->resample_K > 0)
+        for (int32_t t = 0; t < T; ++t)
+            if (offs[t + 1] == offs[t]) return fail(HJCD_E_INVALID, "target %d has no seeds to resample", t);
     if (robot_of_target)
         for (int32_t t = 0; t < T; ++t)
             if (robot_of_target[t] < 0 || robot_of_target[t] >= n_robots)
@@ -264,17 +309,30 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
     p->solved = solved;
     group_targets(n_robots, T, robot_of_target, offs, p->grp);
     for (int ri = 0; ri < n_robots; ++ri) {
-        p->choice[ri].variant = 0;
+        p->choice[ri].variant = params->polish_variant;
         p->choice[ri].block_threads = 256;
         p->choice[ri].ms = 0.f;
         p->choice[ri].seeds = p->grp.voffs[p->grp.rb_tb[ri + 1]] - p->grp.voffs[p->grp.rb_tb[ri]];
     }
+    p->resample = params->resample_K > 0;
+    p->K = p->resample ? params->resample_K : 0;
+    p->Bp = p->resample ? (params->resample_B / p->K) * p->K : 0;
+    p->S2 = (int64_t)T * p->Bp;
     const size_t S1 = (size_t)std::max<int64_t>(p->S, 1);
+    const size_t Sf = (size_t)std::max<int64_t>(p->resample ? p->S2 : p->S, 1);  // slots of the final stage
     if ((s = dalloc(&p->d_voffs, T + 1)) != HJCD_OK || (s = dalloc(&p->d_coffs, T + 1)) != HJCD_OK ||
         (s = dalloc(&p->d_perm, T)) != HJCD_OK || (s = dalloc(&p->qw, (size_t)p->n_max * S1)) != HJCD_OK ||
-        (s = dalloc(&p->ep, S1)) != HJCD_OK || (s = dalloc(&p->eo, S1)) != HJCD_OK ||
-        (s = dalloc(&p->cost, S1)) != HJCD_OK || (s = dalloc(&p->fl, S1)) != HJCD_OK)
+        (s = dalloc(&p->ep, std::max(S1, Sf))) != HJCD_OK || (s = dalloc(&p->eo, std::max(S1, Sf))) != HJCD_OK ||
+        (s = dalloc(&p->cost, S1)) != HJCD_OK || (s = dalloc(&p->fl, Sf)) != HJCD_OK)
         return bail(s);
+    std::vector<int64_t> voffs2;
+    if (p->resample) {
+        if ((s = dalloc(&p->d_voffs2, T + 1)) != HJCD_OK || (s = dalloc(&p->rank, (size_t)T * p->K)) != HJCD_OK ||
+            (s = dalloc(&p->qw2, (size_t)p->n_max * Sf)) != HJCD_OK || (s = dalloc(&p->cost2, Sf)) != HJCD_OK)
+            return bail(s);
+        voffs2.resize(T + 1);
+        for (int32_t b = 0; b <= T; ++b) voffs2[b] = (int64_t)b * p->Bp;
+    }
     if (hipStreamCreateWithFlags(&p->main, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
         return bail(fail(HJCD_E_DEVICE, "plan stream / event creation failed"));
@@ -289,6 +347,9 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
         hipMemcpyAsync(p->d_coffs, offs, sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, ust) != hipSuccess ||
         (!p->grp.identity &&
          hipMemcpyAsync(p->d_perm, p->grp.perm.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, ust) !=
+             hipSuccess) ||
+        (p->resample &&
+         hipMemcpyAsync(p->d_voffs2, voffs2.data(), sizeof(int64_t) * (T + 1), hipMemcpyHostToDevice, ust) !=
              hipSuccess) ||
         hipStreamSynchronize(ust) != hipSuccess)
         return bail(fail(HJCD_E_DEVICE, "plan upload failed"));
@@ -309,7 +370,7 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
                 hipSuccess)
             return bail(fail(HJCD_E_DEVICE, "seed gather failed"));
         float* qs = nullptr;
-        if ((s = dalloc(&qs, (size_t)p->n_max * S1)) != HJCD_OK) return bail(s);
+        if ((s = dalloc(&qs, (size_t)p->n_max * Sf)) != HJCD_OK) return bail(s);
         for (int ri = 0; ri < n_robots && s == HJCD_OK; ++ri)
             if (p->choice[ri].seeds > 0) s = autotune(p, ri, qs);
         (void)hipStreamSynchronize(p->main);

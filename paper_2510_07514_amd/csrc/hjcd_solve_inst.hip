@@ -18,7 +18,9 @@ namespace hjcd {
 constexpr bool kExactN = HJCD_NM < 8;
 
 // Occupancy variants of the per-seed solve kernels (a launch-shape choice of
-// the autotuner; the arithmetic is the same).  Minimum waves per SIMD:
+// the autotuner and of hjcd_params.polish_variant; both variants compile the
+// same device code, so their results are bit-identical).  Minimum waves per
+// SIMD:
 //   NM <= 8:       variant 0: 3 (at most 168 VGPRs, a few spills; faster than
 //                  the two waves of the unconstrained ~200), variant 1: 2
 //   8 < NM <= 16:  variant 0: 2 (at most 256 VGPRs), variant 1: 1 (as allocated)
@@ -27,8 +29,9 @@ template <int NM, int V>
 struct SolveOcc {
     static constexpr int waves = NM <= 8 ? (V == 0 ? 3 : 2) : NM <= 16 ? (V == 0 ? 2 : 1) : (V == 0 ? 1 : 2);
     // the spread line search needs ~50 more live registers: at three waves per
-    // SIMD they would spill, so that variant keeps the sequential search
-    static constexpr bool spread = !(NM <= 8 && V == 0);
+    // SIMD they would spill, so buckets up to 8 joints keep the sequential
+    // search in both variants
+    static constexpr bool spread = NM > 8;
 };
 
 // ----------------------------------------------------------------------------
@@ -189,11 +192,10 @@ struct CdOcc {
     static constexpr int waves = (NM > 16 && NM <= 24) ? 2 : SolveOcc<NM, 0>::waves;
 };
 
-// Both stages as the arguments say (the stage entry points, resampling).
-template <int NM, int V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM, V>::waves))) void k_solve(
-    SolveArgs a) {
-    solve_body<NM, SolveOcc<NM, V>::spread>(a, a.do_cd != 0, a.do_polish != 0);
+// Seed initialisation only (hjcd_init_seeds): uniform draws written out.
+template <int NM>
+__global__ __launch_bounds__(256) void k_seed(SolveArgs a) {
+    solve_body<NM, false>(a, false, false);
 }
 
 // PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
@@ -290,32 +292,30 @@ template <>
 hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     const int bt = a.block_threads > 0 ? a.block_threads : 256;
     const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
-    const bool cd_only = a.do_cd && !a.do_polish && !a.traj;
-    const bool pol_only = !a.do_cd && a.do_polish && !a.traj;
+    if (a.do_cd && a.do_polish) return hipErrorInvalidValue;  // the stages run as separate launches
     // PJ-IK streams seeds through its waves once the launch holds enough
     // seeds to keep every wave slot busy with several seeds per lane, in the
     // buckets that run one or two waves per SIMD (measured: with three waves
     // per SIMD the other waves already fill the issue slots an idle lane
-    // leaves, and streaming only lengthens the tail)
-    const int64_t sf = HJCD_NM > 16 ? stream_factor(a.map.Sv) : 1;
+    // leaves, and streaming only lengthens the tail).  A launch that records
+    // trajectories keeps one seed per lane; its arithmetic is the same.
+    const int64_t sf = HJCD_NM > 16 && !a.traj ? stream_factor(a.map.Sv) : 1;
     SolveArgs ps = a;
     ps.seeds_per_wave = 64 * sf;
     const int64_t seeds_per_block = ps.seeds_per_wave * (bt / 64);
     const unsigned nbp = (unsigned)((a.map.Sv + seeds_per_block - 1) / seeds_per_block);
-    if (cd_only)
+    if (a.do_cd)
         hipLaunchKernelGGL((k_cd<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
-    else if (pol_only && sf > 1 && a.variant == 1)
+    else if (!a.do_polish)
+        hipLaunchKernelGGL((k_seed<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
+    else if (sf > 1 && a.variant == 1)
         hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1>), dim3(nbp), dim3(bt), 0, st, ps);
-    else if (pol_only && sf > 1)
+    else if (sf > 1)
         hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0>), dim3(nbp), dim3(bt), 0, st, ps);
-    else if (pol_only && a.variant == 1)
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
-    else if (pol_only)
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
     else if (a.variant == 1)
-        hipLaunchKernelGGL((k_solve<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
     else
-        hipLaunchKernelGGL((k_solve<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
     return hipGetLastError();
 }
 

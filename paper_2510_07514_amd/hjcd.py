@@ -35,6 +35,7 @@ SYMBOLS = ("hjcd_ctx_create", "hjcd_ctx_destroy", "hjcd_last_error", "hjcd_param
            "hjcd_version", "hjcd_load_robot", "hjcd_robot_destroy", "hjcd_robot_dof",
            "hjcd_load_scene", "hjcd_scene_destroy", "hjcd_fk", "hjcd_init_seeds", "hjcd_cd",
            "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve",
+           "hjcd_warm_seeds", "hjcd_select_near", "hjcd_solve_near",
            "hjcd_get_stats", "hjcd_plan_create", "hjcd_plan_execute", "hjcd_plan_choice", "hjcd_plan_destroy",
            "hjcd_server_create", "hjcd_server_start", "hjcd_server_submit",
            "hjcd_server_poll", "hjcd_server_result", "hjcd_server_wait", "hjcd_server_get_stats",
@@ -66,7 +67,8 @@ class hjcd_params(C.Structure):
                 ("weight_mode", C.c_int32), ("eps_pol", C.c_float), ("ups_pol", C.c_float),
                 ("sigma", C.c_float), ("mu", C.c_float), ("resample_K", C.c_int32),
                 ("resample_B", C.c_int32), ("top_k", C.c_int32), ("succ_pos", C.c_float),
-                ("succ_ori", C.c_float), ("rng_seed", C.c_uint64), ("collect_stats", C.c_int32)]
+                ("succ_ori", C.c_float), ("rng_seed", C.c_uint64), ("collect_stats", C.c_int32),
+                ("polish_variant", C.c_int32)]
 
 
 class hjcd_stats(C.Structure):
@@ -140,8 +142,13 @@ _lib.hjcd_collide.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp, _vp]
 _lib.hjcd_resample.argtypes = [_vp, _vp, _i32, _vp, _vp, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp]
 _lib.hjcd_select.argtypes = [_vp, _i32, _vp, _i32, _i32, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp,
                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_select_near.argtypes = [_vp, _i32, _vp, _i32, _i32, C.POINTER(hjcd_params), _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hjcd_solve.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                             C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_solve_near.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                 C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_warm_seeds.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, C.POINTER(hjcd_params), _vp, _vp]
 _lib.hjcd_get_stats.argtypes = [_vp, C.POINTER(hjcd_stats)]
 _lib.hjcd_philox.argtypes = [_vp, _vp, _vp, _i64, _vp, _vp]
 _lib.hjcd_plan_create.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp, C.POINTER(hjcd_params),
@@ -378,8 +385,17 @@ def hjcd_select(ctx, seed_offsets, n, n_stride, params, q, cost, err_p, err_o, f
                             _ptr(n_free), _ptr(solved), _stream(stream)))
 
 
+def hjcd_select_near(ctx, seed_offsets, n, n_stride, params, q, cost, err_p, err_o, flag, q_ref, q_out, err_p_out,
+                     err_o_out, flag_out, n_free, solved, stream=None):
+    offs, op = _host(seed_offsets, np.int64)
+    _check(_lib.hjcd_select_near(ctx.handle, int(offs.shape[0] - 1), op, int(n), int(n_stride),
+                                 C.byref(params), _ptr(q), _ptr(cost), _ptr(err_p), _ptr(err_o), _ptr(flag),
+                                 _ptr(q_ref), _ptr(q_out), _ptr(err_p_out), _ptr(err_o_out), _ptr(flag_out),
+                                 _ptr(n_free), _ptr(solved), _stream(stream)))
+
+
 def hjcd_solve(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, err_o, flag, n_free,
-               solved, robot_of_target=None, seeds=None, target_keys=None, stream=None):
+               solved, robot_of_target=None, seeds=None, target_keys=None, stream=None, _fn=None):
     """The whole batched solve; see hjcd_solve in include/hjcd.h."""
     if isinstance(robots, Robot):
         robots = [robots]
@@ -388,10 +404,34 @@ def hjcd_solve(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, 
     rot = None
     if robot_of_target is not None:
         rot, rotp = _host(robot_of_target, np.int32)
-    _check(_lib.hjcd_solve(ctx.handle, len(robots), C.cast(arr, _vp), scene.handle if scene else None,
+    _check((_fn or _lib.hjcd_solve)(ctx.handle, len(robots), C.cast(arr, _vp), scene.handle if scene else None,
                            int(offs.shape[0] - 1), rotp if rot is not None else None, _ptr(targets), op,
                            _ptr(target_keys), _ptr(seeds), C.byref(params), _ptr(q_out), _ptr(err_p),
                            _ptr(err_o), _ptr(flag), _ptr(n_free), _ptr(solved), _stream(stream)))
+
+
+def hjcd_solve_near(ctx, robots, scene, targets, seed_offsets, params, q_ref, q_out, err_p, err_o, flag, n_free,
+                    solved, robot_of_target=None, seeds=None, target_keys=None, stream=None):
+    """The whole solve with the nearest-solution selection around q_ref
+    [T][n_max]; see hjcd_solve_near in include/hjcd.h."""
+    if isinstance(robots, Robot):
+        robots = [robots]
+    arr = (_vp * len(robots))(*[r.handle for r in robots])
+    offs, op = _host(seed_offsets, np.int64)
+    rot, rotp = None, None
+    if robot_of_target is not None:
+        rot, rotp = _host(robot_of_target, np.int32)
+    _check(_lib.hjcd_solve_near(ctx.handle, len(robots), C.cast(arr, _vp), scene.handle if scene else None,
+                                int(offs.shape[0] - 1), rotp, _ptr(targets), op, _ptr(target_keys), _ptr(seeds),
+                                C.byref(params), _ptr(q_ref), _ptr(q_out), _ptr(err_p), _ptr(err_o), _ptr(flag),
+                                _ptr(n_free), _ptr(solved), _stream(stream)))
+
+
+def hjcd_warm_seeds(ctx, robot, q_prev, k, M, params, q_out, target_keys=None, stream=None):
+    """q_prev [T*k][n_stride] -> q_out [n][T*M]; see hjcd_warm_seeds."""
+    T = q_prev.shape[0] // k
+    _check(_lib.hjcd_warm_seeds(ctx.handle, robot.handle, int(T), int(k), int(q_prev.shape[1]), _ptr(q_prev),
+                                int(M), _ptr(target_keys), C.byref(params), _ptr(q_out), _stream(stream)))
 
 
 def hjcd_get_stats(ctx) -> dict:
@@ -508,6 +548,26 @@ def hjcd_server_poll(srv: Server, max_n: int = 1024) -> list:
     n = _i32()
     _check(_lib.hjcd_server_poll(srv.handle, max_n, buf, C.byref(n)))
     return [buf[i].as_dict() for i in range(n.value)]
+
+
+REQUEST_INFO_DTYPE = np.dtype([("request_id", np.int64), ("tag", np.uint64), ("n_targets", np.int32),
+                               ("n_solved", np.int32), ("arrival_s", np.float64), ("admitted_s", np.float64),
+                               ("done_s", np.float64)])
+assert REQUEST_INFO_DTYPE.itemsize == C.sizeof(hjcd_request_info)
+
+
+def hjcd_server_poll_all(srv: Server, chunk: int = 65536) -> np.ndarray:
+    """Every completed request not yet reported, as a numpy structured array
+    (fields of hjcd_request_info), oldest first."""
+    buf = (hjcd_request_info * chunk)()
+    n = _i32()
+    parts = []
+    while True:
+        _check(_lib.hjcd_server_poll(srv.handle, chunk, buf, C.byref(n)))
+        if n.value == 0:
+            break
+        parts.append(np.frombuffer(buf, dtype=REQUEST_INFO_DTYPE, count=n.value).copy())
+    return np.concatenate(parts) if parts else np.zeros(0, REQUEST_INFO_DTYPE)
 
 
 def hjcd_server_result(srv: Server, request_id: int, n_targets: int) -> dict:

@@ -100,6 +100,17 @@ def random_chain(rng: np.random.Generator, n: int, name: str | None = None) -> R
                  np.full(n, -2.9), np.full(n, 2.9), np.eye(4))
 
 
+def chained_panda(copies: int) -> Robot:
+    """6 x copies-DoF chain built from repeated copies of the Panda-like
+    chain's first six joints (DH rows and limits), with the 0.107 m flange as
+    the tool: the DoF-scaling robots of the paper's Sec. V study (12, 18 and
+    24 DoF for 2, 3 and 4 copies).  No link spheres (open world)."""
+    p = panda_like()
+    rep = lambda x: np.tile(np.asarray(x[:6]), copies)
+    return Robot(f"chained_panda{6 * copies}", DH_MODIFIED, rep(p.a), rep(p.d), rep(p.alpha),
+                 np.zeros(6 * copies), rep(p.q_min), rep(p.q_max), _tool_tz(0.107), min_link_gap=0)
+
+
 def planar_chain(lengths, limit: float = PI) -> Robot:
     """Planar nR chain (alpha = 0, d = 0, a = link lengths) in modified DH.
     The last link length is carried by the tool so the end effector sits at
@@ -353,6 +364,42 @@ def config_large(T: int = 100_000, M: int = 256, host_seeds: bool = False) -> Ba
                                               rng_seed=5), 5)
 
 
+def config_dof(dof: int, T: int = 1000, M: int = 1000, host_seeds: bool = False) -> Batch:
+    """DoF scaling (Sec. V, the chained-Panda study): the Panda-like chain
+    (dof = 7) or its chained first six joints (dof = 12, 18, 24), T targets x
+    M seeds (the paper's B = 1,000), open world (no obstacles, no self test),
+    20 + 20 iterations, top-1."""
+    if dof == 7:
+        robot = panda_like()
+        robot.min_link_gap = 0
+    elif dof in (12, 18, 24):
+        robot = chained_panda(dof // 6)
+    else:
+        raise ValueError("dof must be 7, 12, 18 or 24")
+    rng = np.random.default_rng(60 + dof)
+    q_star = list(uniform_configs(rng, robot, T))
+    offs = np.arange(T + 1, dtype=np.int64) * M
+    seeds = _seeds_soa(rng, [robot], np.zeros(T, np.int32), offs) if host_seeds else None
+    return Batch(f"dof_{robot.name}_{T}x{M}", [robot], np.zeros(T, np.int32), q_star, offs,
+                 seeds, empty_scene(), default_params(top_k=1, rng_seed=60 + dof), 60 + dof)
+
+
+def tracking_paths(robot: Robot, tracks: int, steps: int, seed: int = 7, amp: float = 0.3,
+                   period: int = 100) -> np.ndarray:
+    """Joint-space paths for the tracking workload (Sec. V demonstration: a
+    pose that moves along a path): per track a centre uniform in the limits
+    shrunk by amp, and q*(s) = centre + amp sin(2 pi s / period + phase) per
+    joint, phase uniform; returns float32 [steps][tracks][n] (inside the
+    limits).  A target on the path is FK(q*(s))."""
+    rng = np.random.default_rng(seed)
+    lo, hi = robot.q_min + amp, robot.q_max - amp
+    centre = lo + (hi - lo) * rng.uniform(size=(tracks, robot.dof))
+    phase = rng.uniform(0.0, 2.0 * PI, size=(tracks, robot.dof))
+    s = np.arange(steps)[:, None, None]
+    q = centre[None] + amp * np.sin(2.0 * PI * s / period + phase[None])
+    return np.clip(q, robot.q_min, robot.q_max).astype(np.float32)
+
+
 def serving_stream(rate: float, duration: float, seed: int = 4):
     """Poisson request stream for the serving workload: arrival times (s),
     targets per request U{1..16} (Panda-like, FK of uniform configs), a
@@ -368,7 +415,8 @@ def serving_stream(rate: float, duration: float, seed: int = 4):
     n_req = t.shape[0]
     n_tgt = rng.integers(1, 17, size=n_req)
     budget = log_uniform_int(rng, 32, 1024, n_req)
-    q_star = [uniform_configs(rng, robot, int(k)) for k in n_tgt]
+    q_all = uniform_configs(rng, robot, int(n_tgt.sum()))
+    q_star = np.split(q_all, np.cumsum(n_tgt)[:-1])
     return dict(robot=robot, scene=scene, arrival=t, n_targets=n_tgt, seeds_per_target=budget,
                 q_star=q_star, params=default_params(top_k=1, rng_seed=4))
 
@@ -378,4 +426,8 @@ CONFIGS = {
     "batched": config_batched,
     "uneven": config_uneven,
     "large": config_large,
+    "dof7": lambda **kw: config_dof(7, **kw),
+    "dof12": lambda **kw: config_dof(12, **kw),
+    "dof18": lambda **kw: config_dof(18, **kw),
+    "dof24": lambda **kw: config_dof(24, **kw),
 }

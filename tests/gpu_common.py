@@ -70,6 +70,16 @@ def compare_trajectories(gpu_traj, orc, n, shadows=None):
     return worst <= TOL_TRAJ, k, worst
 
 
+def endpoint_ok(row, n, which, params):
+    """The stage's own success test on the last trajectory row [theta, |r_p|,
+    phi]: PO-CCD's exit tolerances (eps_cd, nu_cd) for CD, 1 mm / 1 deg for
+    PJ-IK."""
+    ep, phi = float(row[n]), float(row[n + 1])
+    if which == "cd":
+        return ep < params["eps_cd"] and phi < params["nu_cd"]
+    return ep <= params["succ_pos"] and phi <= params["succ_ori"]
+
+
 def quat_close(a, b):
     """Distance between unit quaternions up to sign."""
     a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
@@ -77,4 +87,4 @@ def quat_close(a, b):
 
 
 __all__ = ["TAU_DEC", "TOL_TRAJ", "SHADOW_FRAC", "N_SHADOWS", "say", "cuda", "soa", "targets_soa",
-           "first_tie", "shadow_horizon", "compare_trajectories", "quat_close", "math"]
+           "first_tie", "shadow_horizon", "compare_trajectories", "endpoint_ok", "quat_close", "math"]
