@@ -18,7 +18,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hjcd_oracle.cpp")
-LIB = os.path.join(HERE, "liboracle.so")
+# HJCD_ORACLE_LIBRARY selects another build of the same source (the tests'
+# sanitizer build); it is used as given and never rebuilt here.
+LIB_OVERRIDE = os.environ.get("HJCD_ORACLE_LIBRARY")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "liboracle.so")
 
 ST_INIT, ST_CD, ST_RESAMPLE, ST_POLISH, ST_WARM = 0, 1, 2, 3, 4
 
@@ -79,7 +82,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not LIB_OVERRIDE and (not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
         L = C.CDLL(LIB)
         dp = C.POINTER(C.c_double)

@@ -370,9 +370,6 @@ hjcd_status batched_step(hjcd_server s) {
     }
     HIP_TRY(hipStreamSynchronize(s->stream));
     const double t_done = s->now();
-    s->stats.chunks++;
-    s->resident_sum += (double)resident;
-    s->stats.resident_slots_peak = std::max<int64_t>(s->stats.resident_slots_peak, resident);
 
     // 3. bookkeeping: results, stage transitions, completions
     it = 0;
@@ -409,8 +406,12 @@ hjcd_status batched_step(hjcd_server s) {
         }
     }
     s->active.swap(keep);
-    if (!done.empty()) {
+    {
+        // the statistics are read under the same mutex by hjcd_server_get_stats
         std::unique_lock<std::mutex> lk(s->mu);
+        s->stats.chunks++;
+        s->resident_sum += (double)resident;
+        s->stats.resident_slots_peak = std::max<int64_t>(s->stats.resident_slots_peak, resident);
         for (auto& r : done) finish_request(s, std::move(r));
     }
     return HJCD_OK;
