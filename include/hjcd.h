@@ -265,6 +265,28 @@ hjcd_status hjcd_solve(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots,
                        const float* seeds, const hjcd_params* params, float* q_out, float* err_p,
                        float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): hjcd_solve with the
+ * same arguments, results and errors, whose work arrays (grouped seeds, CD and
+ * PJ-IK state, costs, flags, the layout upload) live in a static device
+ * workspace of HJCD_NOALLOC_SCRATCH_BYTES per device, held from library load
+ * to process end, instead of context buffers grown on demand.  It calls no
+ * allocating routine.  Limits: T <= HJCD_NOALLOC_MAX_TARGETS; the work must
+ * fit the workspace: (n_max + 3) x 4 + 1 bytes per seed slot (also per
+ * resampled slot, plus n_max x 4 per CD seed when resampling) and ~24 bytes
+ * per target, else HJCD_E_INVALID (e.g. 1.6 M seeds of a 7-joint chain);
+ * collect_stats must be 0 (HJCD_E_UNSUPPORTED).  Every call on one device
+ * shares that device's workspace: calls that overlap on one device (other
+ * streams, other contexts, other threads) race and must be serialised by the
+ * caller.  Nothing in the workspace needs to start at zero. */
+#define HJCD_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define HJCD_NOALLOC_MAX_TARGETS 65536
+hjcd_status hjcd_solve_noalloc(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots, hjcd_scene scene,
+                               int32_t T, const int32_t* robot_of_target /* host */, const float* targets,
+                               const int64_t* seed_offsets /* host [T+1] */, const uint32_t* target_keys,
+                               const float* seeds, const hjcd_params* params, float* q_out, float* err_p,
+                               float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream);
+
 /* hjcd_solve whose final selection is hjcd_select_near's order around
  * q_ref [T][n_max] (device): the tracking form of the whole solve. */
 hjcd_status hjcd_solve_near(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots, hjcd_scene scene, int32_t T,

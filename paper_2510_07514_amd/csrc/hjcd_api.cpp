@@ -103,7 +103,37 @@ size_t staging_bytes(std::initializer_list<size_t> parts) {
 
 bool finite_f(float x) { return std::isfinite(x); }
 
-// Pinned staging bytes of a solve's layout upload for T targets.
+// Static workspace of hjcd_solve_noalloc: one copy per device, held from
+// module load to process end.  Host code never uses the symbol's name as an
+// address: hjcd_ctx_create looks up this device's copy once
+// (hipGetSymbolAddress, with the device current) and the solve passes that
+// address to its kernels.
+static __device__ __align__(256) unsigned char scratch[HJCD_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Records this device's copy of `scratch` (the device must be current).
+hjcd_status init_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(HJCD_E_DEVICE, "device %d beyond the scratch table", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return HJCD_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(HJCD_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return HJCD_OK;
+}
+
+void* scratch_of(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
+// Pinned staging bytes every context starts with: enough for the layout
+// upload of hjcd_solve_noalloc at HJCD_NOALLOC_MAX_TARGETS targets.
 size_t layout_staging_bytes(int32_t T) {
     return staging_bytes({sizeof(int64_t) * (T + 1), sizeof(int64_t) * (T + 1), sizeof(int32_t) * (size_t)T,
                           sizeof(int64_t) * (T + 1)});
@@ -322,6 +352,18 @@ hjcd_status hjcd_ctx_create(int device, hjcd_ctx* out) {
             return fail(HJCD_E_DEVICE, "event creation failed");
         }
     }
+    hjcd_status s = init_scratch(device);
+    if (s != HJCD_OK) {
+        hjcd_ctx_destroy(c);
+        return s;
+    }
+    const size_t pin = layout_staging_bytes(HJCD_NOALLOC_MAX_TARGETS);
+    if (hipHostMalloc(&c->pinned, pin, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        hjcd_ctx_destroy(c);
+        return fail(HJCD_E_NOMEM, "pinned host allocation of %zu bytes failed", pin);
+    }
+    c->pinned_cap = pin;
     *out = c;
     return HJCD_OK;
 }
@@ -800,12 +842,13 @@ hjcd_status hjcd_warm_seeds(hjcd_ctx c, hjcd_robot r, int32_t T, int32_t k, int3
 
 // ---- the whole solve --------------------------------------------------------
 
-// The whole solve.  Work arrays come from the context (grown on demand).
+// The whole solve.  Work arrays come from the context (grown on demand) or,
+// with `noalloc`, from this device's static workspace (nothing allocated).
 static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
                               const int32_t* robot_of_target, const float* targets, const int64_t* offs,
                               const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out,
                               float* ep, float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream,
-                              const float* q_ref = nullptr) {
+                              bool noalloc, const float* q_ref = nullptr) {
     hjcd_status s;
     if (n_robots < 1 || n_robots > HJCD_MAX_ROBOTS || !robots)
         return fail(HJCD_E_INVALID, "need 1..%d robots", HJCD_MAX_ROBOTS);
@@ -825,6 +868,10 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
     for (int i = 0; i < n_robots; ++i)
         if ((s = check_robot(c, robots[i])) != HJCD_OK) return s;
     if (sc && sc->ctx != c) return fail(HJCD_E_INVALID, "scene belongs to another context");
+    if (noalloc && p->collect_stats)
+        return fail(HJCD_E_UNSUPPORTED, "hjcd_solve_noalloc collects no statistics (collect_stats must be 0)");
+    if (noalloc && T > HJCD_NOALLOC_MAX_TARGETS)
+        return fail(HJCD_E_INVALID, "T = %d exceeds HJCD_NOALLOC_MAX_TARGETS (%d)", T, HJCD_NOALLOC_MAX_TARGETS);
     if (T == 0) return HJCD_OK;
     if ((s = bind(c)) != HJCD_OK) return s;
     int n_max = 0;
@@ -858,29 +905,56 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
     const size_t sz_flag = std::max<int64_t>(Sf, 1);
     const size_t sz_rank = resample ? sizeof(int32_t) * (size_t)T * K : 0;
     void *w_voffs, *w_voffs2, *w_perm, *w_coffs, *w_qw, *w_qw2, *w_ep, *w_eo, *w_cost, *w_flag, *w_rank;
-    if ((s = ensure(c, c->voffs, sz_voffs)) != HJCD_OK || (s = ensure(c, c->voffs2, sz_voffs)) != HJCD_OK ||
-        (s = ensure(c, c->tperm, sz_perm)) != HJCD_OK || (s = ensure(c, c->coffs, sz_voffs)) != HJCD_OK ||
-        (s = ensure(c, c->q_work, sz_qw)) != HJCD_OK ||
-        (resample && (s = ensure(c, c->q_work2, sz_qw2)) != HJCD_OK) ||
-        (s = ensure(c, c->ep, sz_f)) != HJCD_OK || (s = ensure(c, c->eo, sz_f)) != HJCD_OK ||
-        (s = ensure(c, c->cost, sz_cost)) != HJCD_OK || (s = ensure(c, c->flag, sz_flag)) != HJCD_OK ||
-        (resample && (s = ensure(c, c->rank, sz_rank)) != HJCD_OK))
-        return s;
-    w_voffs = c->voffs.p;
-    w_voffs2 = c->voffs2.p;
-    w_perm = c->tperm.p;
-    w_coffs = c->coffs.p;
-    w_qw = c->q_work.p;
-    w_qw2 = c->q_work2.p;
-    w_ep = c->ep.p;
-    w_eo = c->eo.p;
-    w_cost = c->cost.p;
-    w_flag = c->flag.p;
-    w_rank = c->rank.p;
+    if (!noalloc) {
+        if ((s = ensure(c, c->voffs, sz_voffs)) != HJCD_OK || (s = ensure(c, c->voffs2, sz_voffs)) != HJCD_OK ||
+            (s = ensure(c, c->tperm, sz_perm)) != HJCD_OK || (s = ensure(c, c->coffs, sz_voffs)) != HJCD_OK ||
+            (s = ensure(c, c->q_work, sz_qw)) != HJCD_OK ||
+            (resample && (s = ensure(c, c->q_work2, sz_qw2)) != HJCD_OK) ||
+            (s = ensure(c, c->ep, sz_f)) != HJCD_OK || (s = ensure(c, c->eo, sz_f)) != HJCD_OK ||
+            (s = ensure(c, c->cost, sz_cost)) != HJCD_OK || (s = ensure(c, c->flag, sz_flag)) != HJCD_OK ||
+            (resample && (s = ensure(c, c->rank, sz_rank)) != HJCD_OK))
+            return s;
+        w_voffs = c->voffs.p;
+        w_voffs2 = c->voffs2.p;
+        w_perm = c->tperm.p;
+        w_coffs = c->coffs.p;
+        w_qw = c->q_work.p;
+        w_qw2 = c->q_work2.p;
+        w_ep = c->ep.p;
+        w_eo = c->eo.p;
+        w_cost = c->cost.p;
+        w_flag = c->flag.p;
+        w_rank = c->rank.p;
+    } else {
+        // carve this device's static workspace into 256-byte aligned pieces;
+        // every piece is written before it is read, so nothing needs clearing
+        char* base = (char*)scratch_of(c->device);
+        if (!base) return fail(HJCD_E_DEVICE, "no static workspace address for device %d", c->device);
+        size_t off = 0;
+        auto take = [&](size_t bytes) -> void* {
+            void* q = base + off;
+            off += (bytes + 255) & ~size_t(255);
+            return q;
+        };
+        w_voffs = take(sz_voffs);
+        w_voffs2 = take(sz_voffs);
+        w_perm = take(sz_perm);
+        w_coffs = take(sz_voffs);
+        w_rank = take(sz_rank);
+        w_qw = take(sz_qw);
+        w_qw2 = take(sz_qw2);
+        w_ep = take(sz_f);
+        w_eo = take(sz_f);
+        w_cost = take(sz_cost);
+        w_flag = take(sz_flag);
+        if (off > (size_t)HJCD_NOALLOC_SCRATCH_BYTES)
+            return fail(HJCD_E_INVALID, "the solve needs %zu bytes of workspace; HJCD_NOALLOC_SCRATCH_BYTES is %zu",
+                        off, (size_t)HJCD_NOALLOC_SCRATCH_BYTES);
+    }
     StatScope ss{c, st, false};
     if ((s = ss.begin(p->collect_stats != 0, S)) != HJCD_OK) return s;
     {
-        Staging sg{c, st};
+        Staging sg{c, st, !noalloc};
         if ((s = sg.begin(layout_staging_bytes(T))) != HJCD_OK) return s;
         if ((s = sg.put(w_voffs, voffs.data(), sz_voffs)) != HJCD_OK) return s;
         if (resample && (s = sg.put(w_voffs2, voffs2.data(), sz_voffs)) != HJCD_OK) return s;
@@ -1066,7 +1140,7 @@ hjcd_status hjcd_solve(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, h
                        const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out, float* ep,
                        float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream) {
     return solve_impl(c, n_robots, robots, sc, T, robot_of_target, targets, offs, tkeys, seeds, p, q_out, ep, eo, flag,
-                      n_free, solved, stream);
+                      n_free, solved, stream, false);
 }
 
 hjcd_status hjcd_solve_near(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
@@ -1076,7 +1150,15 @@ hjcd_status hjcd_solve_near(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robo
                             void* stream) {
     if (T > 0 && !q_ref) return fail(HJCD_E_INVALID, "q_ref is required");
     return solve_impl(c, n_robots, robots, sc, T, robot_of_target, targets, offs, tkeys, seeds, p, q_out, ep, eo, flag,
-                      n_free, solved, stream, q_ref);
+                      n_free, solved, stream, false, q_ref);
+}
+
+hjcd_status hjcd_solve_noalloc(hjcd_ctx c, int32_t n_robots, const hjcd_robot* robots, hjcd_scene sc, int32_t T,
+                               const int32_t* robot_of_target, const float* targets, const int64_t* offs,
+                               const uint32_t* tkeys, const float* seeds, const hjcd_params* p, float* q_out,
+                               float* ep, float* eo, uint8_t* flag, int32_t* n_free, uint8_t* solved, void* stream) {
+    return solve_impl(c, n_robots, robots, sc, T, robot_of_target, targets, offs, tkeys, seeds, p, q_out, ep, eo, flag,
+                      n_free, solved, stream, true);
 }
 
 hjcd_status hjcd_get_stats(hjcd_ctx c, hjcd_stats* out) {

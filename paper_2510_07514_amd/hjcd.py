@@ -34,7 +34,7 @@ HJCD_MAX_TOPK = 64
 SYMBOLS = ("hjcd_ctx_create", "hjcd_ctx_destroy", "hjcd_last_error", "hjcd_params_default",
            "hjcd_version", "hjcd_load_robot", "hjcd_robot_destroy", "hjcd_robot_dof",
            "hjcd_load_scene", "hjcd_scene_destroy", "hjcd_fk", "hjcd_init_seeds", "hjcd_cd",
-           "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve",
+           "hjcd_polish", "hjcd_collide", "hjcd_resample", "hjcd_select", "hjcd_solve", "hjcd_solve_noalloc",
            "hjcd_warm_seeds", "hjcd_select_near", "hjcd_solve_near",
            "hjcd_get_stats", "hjcd_plan_create", "hjcd_plan_execute", "hjcd_plan_choice", "hjcd_plan_destroy",
            "hjcd_server_create", "hjcd_server_start", "hjcd_server_submit",
@@ -146,6 +146,7 @@ _lib.hjcd_select_near.argtypes = [_vp, _i32, _vp, _i32, _i32, C.POINTER(hjcd_par
                                   _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hjcd_solve.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                             C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hjcd_solve_noalloc.argtypes = _lib.hjcd_solve.argtypes
 _lib.hjcd_solve_near.argtypes = [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
                                  C.POINTER(hjcd_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hjcd_warm_seeds.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, C.POINTER(hjcd_params), _vp, _vp]
@@ -432,6 +433,15 @@ def hjcd_warm_seeds(ctx, robot, q_prev, k, M, params, q_out, target_keys=None, s
     T = q_prev.shape[0] // k
     _check(_lib.hjcd_warm_seeds(ctx.handle, robot.handle, int(T), int(k), int(q_prev.shape[1]), _ptr(q_prev),
                                 int(M), _ptr(target_keys), C.byref(params), _ptr(q_out), _stream(stream)))
+
+
+def hjcd_solve_noalloc(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, err_o, flag, n_free,
+                       solved, robot_of_target=None, seeds=None, target_keys=None, stream=None):
+    """hjcd_solve over the library's static device workspace (allocates
+    nothing); see hjcd_solve_noalloc in include/hjcd.h."""
+    hjcd_solve(ctx, robots, scene, targets, seed_offsets, params, q_out, err_p, err_o, flag, n_free, solved,
+               robot_of_target=robot_of_target, seeds=seeds, target_keys=target_keys, stream=stream,
+               _fn=_lib.hjcd_solve_noalloc)
 
 
 def hjcd_get_stats(ctx) -> dict:
