@@ -492,8 +492,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--targets", type=int, default=1000)
     ap.add_argument("--seeds", type=int, default=1024)
-    ap.add_argument("--cpu-targets", type=int, default=384)
-    ap.add_argument("--cpu-single-targets", type=int, default=12)
+    ap.add_argument("--cpu-targets", type=int, default=1000)
+    ap.add_argument("--cpu-single-targets", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")

@@ -123,6 +123,9 @@ typedef struct {
     int32_t polish_variant;  /* launch shape of the PJ-IK kernel: 0 default, 1 the other occupancy
                                 (waves per SIMD 3 / 2 up to 8 joints, 2 / 1 up to 24, 1 / 2 above);
                                 the arithmetic is the same, so results are bit-identical */
+    int32_t cd_lanes_per_seed;  /* PO-CCD lanes per seed: 1 (or 0), or 2 for robots of 9 joints or
+                                   more (a lane pair splits the per-joint candidates; smaller robots
+                                   keep one lane); same steps and decisions either way */
 } hjcd_params;
 
 /* Per-call measurements of the last hjcd_solve / stage call made with
@@ -304,9 +307,9 @@ hjcd_status hjcd_get_stats(hjcd_ctx ctx, hjcd_stats* out);
  * A plan fixes one batch: robots, scene, targets grouped by robot, seed
  * offsets, params and the device buffers every execution reads and writes
  * (the arguments of hjcd_solve).  At creation it uploads the batch layout
- * once, optionally autotunes the per-seed kernel's launch shape per robot
- * (occupancy variant x workgroup size, timed on these buffers, fastest
- * kept), and captures the whole solve into one hipGraph: the robots' solve
+ * once, optionally autotunes the per-seed kernels' launch shapes per robot
+ * (PJ-IK occupancy variant x workgroup size, PO-CCD lanes per seed for
+ * robots of 9 joints or more; timed on these buffers, fastest kept), and captures the whole solve into one hipGraph: the robots' solve
  * and collision kernels on concurrent branches, then the selection.
  * hjcd_plan_execute replays that graph on a stream: one launch for the whole
  * uneven batch.  The results equal hjcd_solve's on the same inputs, bit for
@@ -322,8 +325,10 @@ typedef struct {
     int32_t variant;        /* PJ-IK occupancy: 0 default, 1 the alternative (waves per SIMD
                                0 / 1: 3 / 2 up to 8 joints, 2 / 1 up to 24, 1 / 2 above) */
     int32_t block_threads;  /* workgroup size of the per-seed kernel */
-    float ms;               /* measured time of the chosen shape (0 when not tuned) */
+    float ms;               /* measured time of the chosen PJ-IK shape (0 when not tuned) */
     int64_t seeds;          /* seeds of this robot in the batch */
+    int32_t cd_lanes;       /* PO-CCD lanes per seed chosen (1 or 2) */
+    float cd_ms;            /* measured PO-CCD time with that choice (0 when not tuned) */
 } hjcd_tune_choice;
 
 hjcd_status hjcd_plan_create(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* robots, hjcd_scene scene,

@@ -163,6 +163,8 @@ hjcd_status hjcd::check_params(const hjcd_params* p) {
     if (p->resample_K < 0 || (p->resample_K > 0 && p->resample_B < p->resample_K))
         return fail(HJCD_E_INVALID, "resample needs K >= 0 and B >= K");
     if (p->polish_variant != 0 && p->polish_variant != 1) return fail(HJCD_E_INVALID, "polish_variant must be 0 or 1");
+    if (p->cd_lanes_per_seed < 0 || p->cd_lanes_per_seed > 2)
+        return fail(HJCD_E_INVALID, "cd_lanes_per_seed must be 0, 1 or 2");
     return HJCD_OK;
 }
 
@@ -326,6 +328,7 @@ void hjcd_params_default(hjcd_params* p) {
     p->rng_seed = 0;
     p->collect_stats = 0;
     p->polish_variant = 0;
+    p->cd_lanes_per_seed = 1;
 }
 
 hjcd_status hjcd_ctx_create(int device, hjcd_ctx* out) {
@@ -692,6 +695,7 @@ static hjcd_status stage_common(hjcd_ctx c, hjcd_robot r, int32_t T, const float
     a.kp = kparams(*p);
     a.counters = ss.counters();
     a.variant = p->polish_variant;
+    a.cd_lanes = p->cd_lanes_per_seed == 2 ? 2 : 1;
     HIP_TRY(launch_solve(a, st));
     if ((s = ss.mark(cd ? SS_CD : SS_POLISH)) != HJCD_OK) return s;
     ss.end();
@@ -1018,6 +1022,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
             a.kp = kp;
             a.counters = ss.counters();
             a.variant = p->polish_variant;
+            a.cd_lanes = p->cd_lanes_per_seed == 2 ? 2 : 1;
             return a;
         };
         for (int ri = 0; ri < n_robots; ++ri) {
@@ -1049,6 +1054,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
             a.do_polish = 0;
             a.kp = kp;
             a.counters = ss.counters();
+            a.cd_lanes = p->cd_lanes_per_seed == 2 ? 2 : 1;
             HIP_TRY(launch_solve(a, st));
         }
         if ((s = ss.mark(SS_CD)) != HJCD_OK) return s;
@@ -1081,6 +1087,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
             a.kp = kp;
             a.counters = ss.counters();
             a.variant = p->polish_variant;
+            a.cd_lanes = p->cd_lanes_per_seed == 2 ? 2 : 1;
             HIP_TRY(launch_solve(a, st));
         }
         if ((s = ss.mark(SS_POLISH)) != HJCD_OK) return s;

@@ -442,6 +442,64 @@ __device__ __forceinline__ void write_traj(float* __restrict__ traj, int n, int6
 }
 
 // ----------------------------------------------------------------------------
+// The two PO-CCD candidates of one joint (origin P, axis z, value tj, limits
+// lo..hi) at the pose ee with residual e (Sec. III, Sec. IV-A):
+//  - position, eq. (vec_proj) / (theta_proj) signed about z, clipped: step dp,
+//    score sp = |r_p|^2 after the move (rigid rotation of the EE about z);
+//  - orientation, eq. (ori_update) delta(k) sgn(a_hat . z) phi, clipped: step
+//    dor, ranked by (oV, oW) = (|v'|^2, w'^2) of the moved error quaternion,
+//    which orders like tan^2(phi'/2).
+// (shu, chu): half-angle sine / cosine of the unclipped move dk * phi.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ void cd_candidate(V3 P, V3 z, float tj, float lo, float hi, const Frame& ee, const Err& e,
+                                             const Target& tg, const KParams& kp, float dk, float shu, float chu,
+                                             float& sp, float& dp, float& oV, float& oW, float& dor_out) {
+    const V3 u = ee.p - P;
+    const V3 v = tg.p - P;
+    const float uz = dot(u, z), vz = dot(v, z);
+    const V3 up = axpy(-uz, z, u);
+    const V3 vp = axpy(-vz, z, v);
+    const float du2 = dot(up, up), dv2 = dot(vp, vp);
+    const bool valid = du2 >= kp.proj_eps2 && dv2 >= kp.proj_eps2;
+    // eq. (vec_proj) / (theta_proj), signed about z
+    const float C = dot(up, vp);
+    const float Sg = dot(z, cross(up, vp));
+    const float d = valid ? atan2f(Sg, C) : 0.f;
+    const bool clp = (tj + d > hi) || (tj + d < lo);
+    dp = clp ? clampf(tj + d, lo, hi) - tj : d;
+    const float az = vz - uz;
+    if (!valid) {
+        sp = e.ep2;
+    } else if (!clp) {
+        // the move aligns up with vp: |v - R u|^2 = az^2 + (|vp| - |up|)^2
+        const float dd = sqrtf(dv2) - sqrtf(du2);
+        sp = fmaf(az, az, dd * dd);
+    } else {
+        float sh, ch;
+        sincos_cw(0.5f * dp, &sh, &ch);
+        const float c2 = 1.f - 2.f * sh * sh, s2 = 2.f * sh * ch;
+        const V3 rw = axpy(s2, cross(z, up), c2 * up);
+        const V3 df = vp - rw;
+        sp = fmaf(az, az, dot(df, df));
+    }
+    // eq. (ori_update): delta(k) sgn(a_hat . z) phi
+    const float vzq = e.q.x * z.x + e.q.y * z.y + e.q.z * z.z;
+    const float sg = vzq > 0.f ? 1.f : (vzq < 0.f ? -1.f : 0.f);
+    const float dor = dk * sg * e.phi;
+    const bool clo = (tj + dor > hi) || (tj + dor < lo);
+    float ch = chu, sh = sg * shu;
+    float doc = dor;
+    if (clo) {
+        doc = clampf(tj + dor, lo, hi) - tj;
+        sincos_cw(0.5f * doc, &sh, &ch);
+    }
+    const Quat qn = qmul_conj_axis(e.q, z, ch, sh);
+    oV = qn.x * qn.x + qn.y * qn.y + qn.z * qn.z;
+    oW = qn.w * qn.w;
+    dor_out = doc;
+}
+
+// ----------------------------------------------------------------------------
 // PO-CCD (Alg. PO-CCD, Sec. III, Sec. IV-A) on one seed, iterations
 // [k0, k1).  `live` is false for padding lanes; they run the uniform control
 // flow with no effect.  `frozen` carries the exit state across calls (a
@@ -490,56 +548,9 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                     dP[j] = 0.f;
                     dO[j] = 0.f;
                     if (j < n) {
-                        const V3 z = Z[j];
-                        const V3 u = ee.p - P[j];
-                        const V3 v = tg.p - P[j];
-                        const float uz = dot(u, z), vz = dot(v, z);
-                        const V3 up = axpy(-uz, z, u);
-                        const V3 vp = axpy(-vz, z, v);
-                        const float du2 = dot(up, up), dv2 = dot(vp, vp);
-                        const bool valid = du2 >= kp.proj_eps2 && dv2 >= kp.proj_eps2;
-                        // eq. (vec_proj) / (theta_proj), signed about z
-                        const float C = dot(up, vp);
-                        const float Sg = dot(z, cross(up, vp));
-                        const float d = valid ? atan2f(Sg, C) : 0.f;
-                        const float lo = rb->lo[j], hi = rb->hi[j];
-                        const float tj = th[j];
-                        const bool clp = (tj + d > hi) || (tj + d < lo);
-                        const float dp = clp ? clampf(tj + d, lo, hi) - tj : d;
-                        float sp;
-                        const float az = vz - uz;
-                        if (!valid) {
-                            sp = e.ep2;
-                        } else if (!clp) {
-                            // the move aligns up with vp: |v - R u|^2 = az^2 + (|vp| - |up|)^2
-                            const float dd = sqrtf(dv2) - sqrtf(du2);
-                            sp = fmaf(az, az, dd * dd);
-                        } else {
-                            float sh, ch;
-                            sincos_cw(0.5f * dp, &sh, &ch);
-                            const float c2 = 1.f - 2.f * sh * sh, s2 = 2.f * sh * ch;
-                            const V3 rw = axpy(s2, cross(z, up), c2 * up);
-                            const V3 df = vp - rw;
-                            sp = fmaf(az, az, dot(df, df));
-                        }
-                        sPq[j] = sp;
-                        dP[j] = dp;
-                        spmin = fminf(spmin, sp);
-                        // eq. (ori_update): delta(k) sgn(a_hat . z) phi
-                        const float vzq = e.q.x * z.x + e.q.y * z.y + e.q.z * z.z;
-                        const float sg = vzq > 0.f ? 1.f : (vzq < 0.f ? -1.f : 0.f);
-                        const float dor = dk * sg * e.phi;
-                        const bool clo = (tj + dor > hi) || (tj + dor < lo);
-                        float ch = chu, sh = sg * shu;
-                        float doc = dor;
-                        if (clo) {
-                            doc = clampf(tj + dor, lo, hi) - tj;
-                            sincos_cw(0.5f * doc, &sh, &ch);
-                        }
-                        const Quat qn = qmul_conj_axis(e.q, z, ch, sh);
-                        oV[j] = qn.x * qn.x + qn.y * qn.y + qn.z * qn.z;
-                        oW[j] = qn.w * qn.w;
-                        dO[j] = doc;
+                        cd_candidate(P[j], Z[j], th[j], rb->lo[j], rb->hi[j], ee, e, tg, kp, dk, shu, chu, sPq[j],
+                                     dP[j], oV[j], oW[j], dO[j]);
+                        spmin = fminf(spmin, sPq[j]);
                         // tan^2(phi'_j / 2) < tan^2(phi'_best / 2), cross-multiplied
                         if (oV[j] * bw < bv * oW[j]) {
                             bv = oV[j];
@@ -638,6 +649,262 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
     fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
     out_err = residual(ee, tg);
     if (live) write_traj<NM>(traj, n, S, s, k1, th, sqrtf(out_err.ep2), out_err.phi);
+}
+
+// ----------------------------------------------------------------------------
+// PO-CCD with two lanes per seed (lane pairs 2i, 2i+1 of a wave), for long
+// chains: both lanes hold the joint vector and walk the whole chain, the even
+// lane keeps the frames and candidates of joints [0, NM/2), the odd lane
+// those of [NM/2, NM), so the per-joint state of a lane is half that of
+// po_ccd.  The picks are combined across the pair by shuffles in the same
+// order po_ccd scans the joints (lowest joint first), so both lanes take the
+// same steps, draws and decisions as po_ccd.
+// ----------------------------------------------------------------------------
+// FK (eq. fk) keeping the joint origins and axes of this lane's half:
+// P0[k], Z0[k] = joint k (even lane) or joint k + NM/2 (odd lane).
+template <int NM, typename RB>
+__device__ __forceinline__ void fk_chain_half(RB rb, int n, const float* th, bool odd, V3* P0, V3* Z0, Frame& ee) {
+    constexpr int H = NM / 2;
+    Frame T = identity_frame();
+    auto keep = [&](int i, const Frame& F) {
+        if (i < H) {
+            if (!odd) {
+                P0[i] = F.p;
+                Z0[i] = F.Z;
+            }
+        } else {
+            if (odd) {
+                P0[i - H] = F.p;
+                Z0[i - H] = F.Z;
+            }
+        }
+    };
+    if (rb->conv == 0) {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                float s, c;
+                sincos_cw(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                T.p = axpy(rb->pz[i], T.Z, axpy(rb->py[i], T.Y, axpy(rb->px[i], T.X, T.p)));
+                V3 Yb = axpy(sa, T.Z, ca * T.Y);
+                V3 Zb = axpy(-sa, T.Y, ca * T.Z);
+                V3 Xn = axpy(s, Yb, c * T.X);
+                V3 Yn = axpy(-s, T.X, c * Yb);
+                T.X = Xn;
+                T.Y = Yn;
+                T.Z = Zb;
+                keep(i, T);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NM; ++i) {
+            if (i < n) {
+                keep(i, T);
+                float s, c;
+                sincos_cw(th[i] + rb->off[i], &s, &c);
+                const float ca = rb->ca[i], sa = rb->sa[i];
+                V3 Xb = axpy(s, T.Y, c * T.X);
+                V3 Yb = axpy(-s, T.X, c * T.Y);
+                T.p = axpy(rb->d[i], T.Z, axpy(rb->a[i], Xb, T.p));
+                V3 Yn = axpy(sa, T.Z, ca * Yb);
+                V3 Zn = axpy(-sa, Yb, ca * T.Z);
+                T.X = Xb;
+                T.Y = Yn;
+                T.Z = Zn;
+            }
+        }
+    }
+    const auto* tl = rb->tool;
+    ee.p = axpy(tl[11], T.Z, axpy(tl[7], T.Y, axpy(tl[3], T.X, T.p)));
+    if (rb->tool_rot) {
+        ee.X = axpy(tl[8], T.Z, axpy(tl[4], T.Y, tl[0] * T.X));
+        ee.Y = axpy(tl[9], T.Z, axpy(tl[5], T.Y, tl[1] * T.X));
+        ee.Z = axpy(tl[10], T.Z, axpy(tl[6], T.Y, tl[2] * T.X));
+    } else {
+        ee.X = T.X;
+        ee.Y = T.Y;
+        ee.Z = T.Z;
+    }
+}
+
+__device__ __forceinline__ V3 shfl_pair(V3 v) {
+    return mk(__shfl_xor(v.x, 1, 64), __shfl_xor(v.y, 1, 64), __shfl_xor(v.z, 1, 64));
+}
+
+template <int NM>
+__device__ __forceinline__ void po_ccd_pair(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
+                                            uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
+                                            Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
+                                            int k1, Err& out_err) {
+    static_assert(NM % 2 == 0, "lane pairs split an even joint bucket");
+    constexpr int H = NM / 2;
+    const bool odd = (threadIdx.x & 1u) != 0;
+    const int base = odd ? H : 0;  // first joint of this lane's half
+    float last_ep = 0.f, last_phi = 0.f;
+    V3 P0[H], Z0[H];
+    float delta = kp.delta0 * powf(kp.delta_decay, (float)k0);
+    for (int k = k0; k < k1; ++k) {
+        if (wave_all(frozen) && !traj) break;
+        if (!frozen) {
+            Frame ee;
+            fk_chain_half<NM>(rb, n, th, odd, P0, Z0, ee);
+            const Err e = residual(ee, tg);
+            last_ep = sqrtf(e.ep2);
+            last_phi = e.phi;
+            if (e.ep2 < kp.eps_cd2 && e.phi < kp.nu_cd) frozen = true;
+            if (live && !odd) write_traj<NM>(traj, n, S, s, k, th, last_ep, last_phi);
+            if (!frozen) {
+                if (!odd) ++cnt.cd_iters;
+                const float dk = fmaxf(kp.delta_min, delta);
+                float shu, chu;
+                sincos_cw(0.5f * dk * e.phi, &shu, &chu);
+                float sPq[H], dP[H], oV[H], oW[H], dO[H];
+                float spmin = 3.4e38f;
+                float bv = 1.f, bw = 0.f;
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    const int j = base + i;
+                    sPq[i] = 3.4e38f;
+                    oV[i] = 1.f;
+                    oW[i] = 0.f;
+                    dP[i] = 0.f;
+                    dO[i] = 0.f;
+                    if (j < n) {
+                        const float tj = odd ? th[i + H] : th[i];
+                        const float lo = odd ? rb->lo[i + H] : rb->lo[i];
+                        const float hi = odd ? rb->hi[i + H] : rb->hi[i];
+                        cd_candidate(P0[i], Z0[i], tj, lo, hi, ee, e, tg, kp, dk, shu, chu, sPq[i], dP[i], oV[i],
+                                     oW[i], dO[i]);
+                        spmin = fminf(spmin, sPq[i]);
+                        if (oV[i] * bw < bv * oW[i]) {
+                            bv = oV[i];
+                            bw = oW[i];
+                        }
+                    }
+                }
+                // pair: the smallest position score, and the best orientation
+                // candidate of the lower half unless the upper half's is
+                // strictly better (the joint order of a single scan)
+                spmin = fminf(spmin, __shfl_xor(spmin, 1, 64));
+                {
+                    const float pv = __shfl_xor(bv, 1, 64), pw = __shfl_xor(bw, 1, 64);
+                    const float ve = odd ? pv : bv, we = odd ? pw : bw;
+                    const float vo = odd ? bv : pv, wo = odd ? bw : pw;
+                    const bool up = vo * we < ve * wo;
+                    bv = up ? vo : ve;
+                    bw = up ? wo : we;
+                }
+                const float dlim = sqrtf(spmin) + kp.tie_eps;
+                const float plim = dlim * dlim;
+                const float hlim = 0.5f * (2.f * atan2f(sqrtf(bv), sqrtf(bw)) + kp.tie_eps);
+                const bool oall = hlim >= 1.5707963f;
+                float sT, cT;
+                sincos_cw(oall ? 0.f : hlim, &sT, &cT);
+                const float sT2 = sT * sT, cT2 = cT * cT;
+                int jp = -1, jo = -1;
+                float dpb = 0.f, dob = 0.f;
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    if (base + i < n) {
+                        if (jp < 0 && sPq[i] <= plim) {
+                            jp = base + i;
+                            dpb = dP[i];
+                        }
+                        if (jo < 0 && (oall || oV[i] * cT2 <= oW[i] * sT2)) {
+                            jo = base + i;
+                            dob = dO[i];
+                        }
+                    }
+                }
+                // the lowest pick of the pair
+                {
+                    const int pjp = __shfl_xor(jp, 1, 64), pjo = __shfl_xor(jo, 1, 64);
+                    const float pdp = __shfl_xor(dpb, 1, 64), pdo = __shfl_xor(dob, 1, 64);
+                    const int ejp = odd ? pjp : jp, ojp = odd ? jp : pjp;
+                    const float edp = odd ? pdp : dpb, odp = odd ? dpb : pdp;
+                    const int ejo = odd ? pjo : jo, ojo = odd ? jo : pjo;
+                    const float edo = odd ? pdo : dob, odo = odd ? dob : pdo;
+                    jp = ejp >= 0 ? ejp : ojp;
+                    dpb = ejp >= 0 ? edp : odp;
+                    jo = ejo >= 0 ? ejo : ojo;
+                    dob = ejo >= 0 ? edo : odo;
+                }
+                int ja = jp, jb = jo;
+                float da = dpb, db = dob;
+                if (jp == jo) {
+                    if (fabsf(dpb) >= fabsf(dob)) {
+                        db = 0.f;
+                    } else {
+                        da = 0.f;
+                    }
+                    jb = ja;
+                    da = da + db;
+                    db = 0.f;
+                } else if (jo < jp) {
+                    ja = jo;
+                    jb = jp;
+                    da = dob;
+                    db = dpb;
+                }
+                // origins and axes of the moved joints from the lane that keeps them
+                V3 Pa = P0[0], Za = Z0[0], Pb = P0[0], Zb = Z0[0];
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    if (base + i == ja) {
+                        Pa = P0[i];
+                        Za = Z0[i];
+                    }
+                    if (base + i == jb) {
+                        Pb = P0[i];
+                        Zb = Z0[i];
+                    }
+                }
+                {
+                    const bool own_a = odd == (ja >= H), own_b = odd == (jb >= H);
+                    const V3 qPa = shfl_pair(Pa), qZa = shfl_pair(Za), qPb = shfl_pair(Pb), qZb = shfl_pair(Zb);
+                    if (!own_a) {
+                        Pa = qPa;
+                        Za = qZa;
+                    }
+                    if (!own_b) {
+                        Pb = qPb;
+                        Zb = qZb;
+                    }
+                }
+                float sha, cha, shb, chb;
+                sincos_cw(0.5f * da, &sha, &cha);
+                sincos_cw(0.5f * db, &shb, &chb);
+                V3 ph = Pb + rot_half(Zb, chb, shb, ee.p - Pb);
+                ph = Pa + rot_half(Za, cha, sha, ph - Pa);
+                Quat qh = qmul_conj_axis(qmul_conj_axis(e.q, Zb, chb, shb), Za, cha, sha);
+                const V3 rph = tg.p - ph;
+                const float h2p = dot(rph, rph);
+                const float hs = sqrtf(qh.x * qh.x + qh.y * qh.y + qh.z * qh.z);
+                const float hphi = 2.f * atan2f(hs, fabsf(qh.w));
+                const bool acc = (e.ep2 - h2p > kp.gamma) || (e.phi * e.phi - hphi * hphi > kp.gamma);
+                if (acc) {
+#pragma unroll
+                    for (int j = 0; j < NM; ++j) {
+                        if (j == ja) th[j] += da;
+                        if (j == jb) th[j] += db;
+                    }
+                } else {
+                    perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_CD, (uint32_t)k, kp.mu, kp.sigma);
+                    if (!odd) ++cnt.cd_perturb;
+                }
+            }
+        } else if (live && !odd) {
+            write_traj<NM>(traj, n, S, s, k, th, last_ep, last_phi);
+        }
+        delta *= kp.delta_decay;
+    }
+    Frame ee;
+    V3 Pd[1], Zd[1];
+    fk_chain<NM, false>(rb, n, th, Pd, Zd, ee);
+    out_err = residual(ee, tg);
+    if (live && !odd) write_traj<NM>(traj, n, S, s, k1, th, sqrtf(out_err.ep2), out_err.phi);
 }
 
 // ----------------------------------------------------------------------------

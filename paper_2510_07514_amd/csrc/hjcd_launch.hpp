@@ -57,6 +57,7 @@ struct SolveArgs {
     int32_t variant;         // occupancy variant of PJ-IK (0 default, 1 the alternative)
     int32_t block_threads;   // workgroup size: 64, 128 or 256 (0 = 256)
     int64_t seeds_per_wave;  // PJ-IK seed streaming: seeds per wave (set by the launch)
+    int32_t cd_lanes;        // lanes per seed of PO-CCD: 1, or 2 (buckets of 12 joints and more)
 };
 
 // Seeds per lane of a PJ-IK launch over Sv seeds: Sv / (8192 x 64) between 1

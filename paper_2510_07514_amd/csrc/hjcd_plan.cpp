@@ -136,6 +136,7 @@ SolveArgs solve_args(hjcd_plan p, int ri, int stage) {
     a.counters = nullptr;
     a.variant = p->choice[ri].variant;
     a.block_threads = stage == 1 ? p->choice[ri].block_threads : 256;
+    a.cd_lanes = p->choice[ri].cd_lanes;
     return a;
 }
 
@@ -217,10 +218,48 @@ hjcd_status autotune(hjcd_plan p, int ri, float* qs) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // PO-CCD lanes per seed (robots of 9 joints or more): one warm-up and two
+    // timed launches each; both write the same results into qw
+    {
+        const int nl = p->robots[ri]->n >= 9 ? 2 : 1;
+        float best_cd = 3.4e38f;
+        int best_lanes = 1;
+        // caller seeds regrouped into qw are updated in place by PO-CCD: they
+        // are gathered again before every launch (the gathers are timed too)
+        const bool gathered = p->seeds && !p->grp.identity;
+        auto cd_once = [&]() -> hipError_t {
+            if (gathered) {
+                const hipError_t g = launch_gather(p->n_max, p->T, p->d_coffs, p->d_voffs, p->d_perm, p->S, p->S,
+                                                   p->seeds, p->qw, p->main);
+                if (g != hipSuccess) return g;
+            }
+            return launch_solve(solve_args(p, ri, 0), p->main);
+        };
+        for (int l = 1; l <= nl; ++l) {
+            p->choice[ri].cd_lanes = l;
+            HIP_TRY(cd_once());
+            HIP_TRY(hipEventRecord(e0, p->main));
+            for (int r = 0; r < 2; ++r) HIP_TRY(cd_once());
+            HIP_TRY(hipEventRecord(e1, p->main));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms *= 0.5f;
+            if (ms < best_cd) {
+                best_cd = ms;
+                best_lanes = l;
+            }
+        }
+        p->choice[ri].cd_lanes = best_lanes;
+        p->choice[ri].cd_ms = best_cd;
+    }
     hjcd_tune_choice best = p->choice[ri];
     best.ms = 3.4e38f;
-    // PO-CCD once; every timed PJ-IK launch then polishes the same CD
-    // results (read from qw) into the scratch rows `qs`
+    // PO-CCD once more from the original seeds; every timed PJ-IK launch then
+    // polishes the same CD results (read from qw) into the scratch rows `qs`
+    if (p->seeds && !p->grp.identity)
+        HIP_TRY(launch_gather(p->n_max, p->T, p->d_coffs, p->d_voffs, p->d_perm, p->S, p->S, p->seeds, p->qw,
+                              p->main));
     HIP_TRY(launch_solve(solve_args(p, ri, 0), p->main));
     if (p->resample) HIP_TRY(launch_between(p, ri, p->main));
     for (int v = 0; v < 2; ++v) {
@@ -311,6 +350,8 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
     for (int ri = 0; ri < n_robots; ++ri) {
         p->choice[ri].variant = params->polish_variant;
         p->choice[ri].block_threads = 256;
+        p->choice[ri].cd_lanes = robots[ri]->n >= 9 && params->cd_lanes_per_seed == 2 ? 2 : 1;
+        p->choice[ri].cd_ms = 0.f;
         p->choice[ri].ms = 0.f;
         p->choice[ri].seeds = p->grp.voffs[p->grp.rb_tb[ri + 1]] - p->grp.voffs[p->grp.rb_tb[ri]];
     }

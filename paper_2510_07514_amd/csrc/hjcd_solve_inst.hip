@@ -190,7 +190,45 @@ struct PolishOcc {
 template <int NM>
 struct CdOcc {
     static constexpr int waves = (NM > 16 && NM <= 24) ? 2 : SolveOcc<NM, 0>::waves;
+    // two lanes per seed hold half the per-joint state; allocation without a
+    // bound (device assembly of this build): ~270 VGPRs at 20 joints, ~310 at
+    // 24 (one lane: ~470 and more), so two waves per SIMD spill 8 and 47
+    // registers there (one lane: 214 and 481); 3 waves up to 16 joints
+    static constexpr int pair_waves = NM <= 16 ? 3 : (NM <= 24 ? 2 : 1);
 };
+
+// PO-CCD with two lanes per seed (po_ccd_pair), buckets of 12 joints and more:
+// lane 2v and 2v + 1 share seed v; the even lane writes the result.
+constexpr bool kPairCd = HJCD_NM >= 12;
+
+template <int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::pair_waves))) void k_cd_pair(
+    SolveArgs a) {
+    const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
+    const bool live = v < a.map.Sv;
+    const bool even = (threadIdx.x & 1u) == 0;
+    const int n = a.n;
+    Slot sl;
+    if (live) {
+        sl = map_lane(a.map, v);
+    } else {
+        sl.s = 0;
+        sl.t = 0;
+        sl.m = 0;
+        sl.tkey = 0;
+    }
+    Target tg{};
+    if (a.targets) tg = load_target(a.targets, a.map.T, sl.t);
+    float th[NM];
+    init_seed<NM>(a, n, sl, live, th);
+    Counters cnt;
+    Err e{};
+    bool frozen = !live;
+    po_ccd_pair<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s, 0,
+                    a.kp.cd_sweeps, e);
+    if (live && even) write_seed<NM>(a, n, th, e, sl.s);
+    flush_counters(cnt, a.counters, a.counters != nullptr);
+}
 
 // Seed initialisation only (hjcd_init_seeds): uniform draws written out.
 template <int NM>
@@ -304,7 +342,14 @@ hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     ps.seeds_per_wave = 64 * sf;
     const int64_t seeds_per_block = ps.seeds_per_wave * (bt / 64);
     const unsigned nbp = (unsigned)((a.map.Sv + seeds_per_block - 1) / seeds_per_block);
-    if (a.do_cd)
+    bool pair_cd = false;
+    if constexpr (kPairCd) pair_cd = a.do_cd && a.cd_lanes == 2;  // smaller buckets keep one lane
+    if (pair_cd) {
+        if constexpr (kPairCd) {
+            const unsigned nb2 = (unsigned)((2 * a.map.Sv + bt - 1) / bt);
+            hipLaunchKernelGGL((k_cd_pair<HJCD_NM>), dim3(nb2), dim3(bt), 0, st, a);
+        }
+    } else if (a.do_cd)
         hipLaunchKernelGGL((k_cd<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
     else if (!a.do_polish)
         hipLaunchKernelGGL((k_seed<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);

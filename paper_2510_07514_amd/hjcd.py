@@ -68,7 +68,7 @@ class hjcd_params(C.Structure):
                 ("sigma", C.c_float), ("mu", C.c_float), ("resample_K", C.c_int32),
                 ("resample_B", C.c_int32), ("top_k", C.c_int32), ("succ_pos", C.c_float),
                 ("succ_ori", C.c_float), ("rng_seed", C.c_uint64), ("collect_stats", C.c_int32),
-                ("polish_variant", C.c_int32)]
+                ("polish_variant", C.c_int32), ("cd_lanes_per_seed", C.c_int32)]
 
 
 class hjcd_stats(C.Structure):
@@ -89,7 +89,8 @@ HJCD_SERVE_PLAIN = 1
 
 
 class hjcd_tune_choice(C.Structure):
-    _fields_ = [("variant", C.c_int32), ("block_threads", C.c_int32), ("ms", C.c_float), ("seeds", C.c_int64)]
+    _fields_ = [("variant", C.c_int32), ("block_threads", C.c_int32), ("ms", C.c_float), ("seeds", C.c_int64),
+                ("cd_lanes", C.c_int32), ("cd_ms", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

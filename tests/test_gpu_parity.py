@@ -215,12 +215,12 @@ def _stage_case(H, ctx, rob, T, M, seed, params, near=None):
     return tg, seeds, offs
 
 
-def _run_stage(H, ctx, rob, which, tg, seeds, offs, params, variant=0):
+def _run_stage(H, ctx, rob, which, tg, seeds, offs, params, variant=0, cd_lanes=1):
     import torch
     rb = H.hjcd_load_robot(ctx, rob)
     n, S = rob.dof, int(offs[-1])
     K = params["cd_sweeps"] if which == "cd" else params["polish_iters"]
-    p = H.params_from_dict(dict(params, polish_variant=variant), collect_stats=True)
+    p = H.params_from_dict(dict(params, polish_variant=variant, cd_lanes_per_seed=cd_lanes), collect_stats=True)
     q = soa(seeds, n)
     ep = torch.zeros(S, device="cuda")
     eo = torch.zeros(S, device="cuda")
@@ -282,9 +282,9 @@ class StageParity:
         assert len(self.end_mismatch) <= allowed, self.end_mismatch[:10]
 
 
-def _check_stage(H, ctx, rob, which, T, M, seed, params, near=None, min_rows=0.95, variant=0):
+def _check_stage(H, ctx, rob, which, T, M, seed, params, near=None, min_rows=0.95, variant=0, cd_lanes=1):
     tg, seeds, offs = _stage_case(H, ctx, rob, T, M, seed, params, near)
-    q, ep, eo, traj, st = _run_stage(H, ctx, rob, which, tg, seeds, offs, params, variant)
+    q, ep, eo, traj, st = _run_stage(H, ctx, rob, which, tg, seeds, offs, params, variant, cd_lanes)
     rh = O.RobotHandle(rob)
     fn = O.cd if which == "cd" else O.polish
     n = rob.dof
@@ -352,14 +352,33 @@ def test_long_chain_trajectories(H, ctx, name):
     rob = _robots()[name]
     over, r_cd, r_near, r_far = LONG_CHAINS[name]
     params = W.default_params(**over)
-    say(f"case: long chain {name} ({rob.dof} joints), cd")
-    _check_stage(H, ctx, rob, "cd", T=4, M=32, seed=20, params=params, min_rows=r_cd)
+    for lanes in (1, 2):
+        say(f"case: long chain {name} ({rob.dof} joints), cd, {lanes} lane(s) per seed")
+        _check_stage(H, ctx, rob, "cd", T=4, M=32, seed=20, params=params, min_rows=r_cd, cd_lanes=lanes)
     for v in (0, 1):
         say(f"case: long chain {name}, polish near, variant {v}")
         _check_stage(H, ctx, rob, "polish", T=4, M=32, seed=21, params=params, near=0.05, min_rows=r_near,
                      variant=v)
     say(f"case: long chain {name}, polish far")
     _check_stage(H, ctx, rob, "polish", T=4, M=32, seed=22, params=params, min_rows=r_far)
+
+
+@pytest.mark.parametrize("name", ["random12", "chained18", "random20", "random24", "random32"])
+def test_cd_lane_pairs_bit_identical(H, ctx, name):
+    """PO-CCD with two lanes per seed (each lane keeps half the joints'
+    frames and candidates) takes the steps, draws and decisions of the
+    one-lane kernel: bit-identical trajectories, configurations and errors
+    (a 64-seed tail and frozen seeds included)."""
+    say(f"case: PO-CCD lane pairs {name}")
+    rob = _robots()[name]
+    params = W.default_params(cd_sweeps=30)
+    tg, seeds, offs = _stage_case(H, ctx, rob, 5, 200, 24, params, near=0.02)
+    a = _run_stage(H, ctx, rob, "cd", tg, seeds, offs, params, cd_lanes=1)
+    b = _run_stage(H, ctx, rob, "cd", tg, seeds, offs, params, cd_lanes=2)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    for kk in ("cd_iters", "cd_perturb"):
+        assert a[4][kk] == b[4][kk], kk
 
 
 @pytest.mark.parametrize("name", ["panda", "random12", "random20", "random24", "random32"])
