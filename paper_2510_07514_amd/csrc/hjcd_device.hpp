@@ -203,7 +203,10 @@ __device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int 
 // residual fed to the solver's decisions keeps the correctly rounded forms:
 // a 2-4 ulp residual moved one sensitive PJ-IK trajectory out of the 1e-4
 // band).
-template <bool FAST = false>
+// CANON = false skips the final sign choice (q and -q are the same rotation);
+// the cost of a trial only needs |w| and |v| of the error quaternion, which do
+// not depend on that sign.
+template <bool FAST = false, bool CANON = true>
 __device__ __forceinline__ Quat quat_of(const Frame& F) {
     const float R00 = F.X.x, R10 = F.X.y, R20 = F.X.z;
     const float R01 = F.Y.x, R11 = F.Y.y, R21 = F.Y.z;
@@ -224,7 +227,7 @@ __device__ __forceinline__ Quat quat_of(const Frame& F) {
     q.x = c0 ? d21 : c1 ? qb : c2 ? s01 : s02;
     q.y = c0 ? d02 : c1 ? s01 : c2 ? qb : s12;
     q.z = c0 ? d10 : c1 ? s02 : c2 ? s12 : qb;
-    if (q.w < 0.f) {
+    if (CANON && q.w < 0.f) {
         q.w = -q.w;
         q.x = -q.x;
         q.y = -q.y;
@@ -989,13 +992,25 @@ __device__ __forceinline__ void jcol(const V3* Jp, const V3* Z, int j, float* c)
     c[5] = Z[j].z;
 }
 
+// Cost 0.5 (|r_p|^2 + phi^2) of a trial configuration: the residual's
+// arithmetic without the sign choices of the quaternions (phi = 2 atan2(|v|,
+// |w|) is the same for q and -q), so the value equals cost_of(residual(...)).
 template <int NM>
 __device__ __forceinline__ float trial_cost(RobotRef rb, int n, const Target& tg,
                                             const float* tt) {
     Frame ee;
     V3 Pd[1], Zd[1];
     fk_chain<NM, false>(rb, n, tt, Pd, Zd, ee);
-    return cost_of(residual(ee, tg));
+    const V3 rp = tg.p - ee.p;
+    const float ep2 = dot(rp, rp);
+    Quat qe = quat_of<false, false>(ee);
+    qe.x = -qe.x;
+    qe.y = -qe.y;
+    qe.z = -qe.z;
+    const Quat q = qmul(tg.q, qe);
+    const float sv = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z);
+    const float phi = 2.f * atan2f(sv, fabsf(q.w));
+    return 0.5f * (ep2 + phi * phi);
 }
 
 // ----------------------------------------------------------------------------
