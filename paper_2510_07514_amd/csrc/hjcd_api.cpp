@@ -103,6 +103,69 @@ size_t staging_bytes(std::initializer_list<size_t> parts) {
 
 bool finite_f(float x) { return std::isfinite(x); }
 
+// Obstacle grid of a scene (see ObstacleGrid): margin 0.3 m (coarse link
+// spheres up to that radius use it), at most 32 cells per axis and cells of
+// at least 0.1 m over the obstacles' bounding boxes grown by the margin.
+constexpr double kGridMargin = 0.3;
+
+bool build_grid(hjcd_scene sc, int32_t n_sph, const float* sph, int32_t n_box, const float* box) {
+    const int32_t no = n_sph + n_box;
+    std::vector<double> lo((size_t)3 * no), hi((size_t)3 * no);
+    double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t o = 0; o < no; ++o)
+        for (int k = 0; k < 3; ++k) {
+            double c, h;
+            if (o < n_sph) {
+                c = sph[4 * o + k];
+                h = sph[4 * o + 3];
+            } else {
+                c = box[6 * (o - n_sph) + k];
+                h = box[6 * (o - n_sph) + 3 + k];
+            }
+            lo[3 * o + k] = c - h - kGridMargin;
+            hi[3 * o + k] = c + h + kGridMargin;
+            glo[k] = std::min(glo[k], lo[3 * o + k]);
+            ghi[k] = std::max(ghi[k], hi[3 * o + k]);
+        }
+    double cell = 0.1;
+    for (int k = 0; k < 3; ++k) cell = std::max(cell, (ghi[k] - glo[k]) / 32.0);
+    int32_t n[3];
+    for (int k = 0; k < 3; ++k) n[k] = std::max(1, (int32_t)std::ceil((ghi[k] - glo[k]) / cell));
+    const int64_t nc = (int64_t)n[0] * n[1] * n[2];
+    std::vector<std::vector<int32_t>> lists((size_t)nc);
+    for (int32_t o = 0; o < no; ++o) {
+        int32_t a[3], b[3];
+        for (int k = 0; k < 3; ++k) {
+            a[k] = std::max(0, (int32_t)std::floor((lo[3 * o + k] - glo[k]) / cell) - 1);
+            b[k] = std::min(n[k] - 1, (int32_t)std::floor((hi[3 * o + k] - glo[k]) / cell) + 1);
+        }
+        // one cell more on each side than the grown box touches: a centre
+        // rounded into a neighbouring cell still finds the obstacle
+        for (int32_t i = a[0]; i <= b[0]; ++i)
+            for (int32_t j = a[1]; j <= b[1]; ++j)
+                for (int32_t k = a[2]; k <= b[2]; ++k) lists[((int64_t)i * n[1] + j) * n[2] + k].push_back(o);
+    }
+    std::vector<int32_t> start((size_t)nc + 1, 0), items;
+    for (int64_t c = 0; c < nc; ++c) {
+        start[c] = (int32_t)items.size();
+        items.insert(items.end(), lists[c].begin(), lists[c].end());
+    }
+    start[nc] = (int32_t)items.size();
+    if (hipMalloc(&sc->g_start, sizeof(int32_t) * start.size()) != hipSuccess ||
+        hipMalloc(&sc->g_items, sizeof(int32_t) * std::max<size_t>(items.size(), 1)) != hipSuccess ||
+        hipMemcpy(sc->g_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (!items.empty() &&
+         hipMemcpy(sc->g_items, items.data(), sizeof(int32_t) * items.size(), hipMemcpyHostToDevice) != hipSuccess))
+        return false;
+    for (int k = 0; k < 3; ++k) {
+        sc->g_lo[k] = (float)glo[k];
+        sc->g_n[k] = n[k];
+    }
+    sc->g_h = (float)cell;
+    sc->g_margin = (float)kGridMargin;
+    return true;
+}
+
 // Static workspace of hjcd_solve_noalloc: one copy per device, held from
 // module load to process end.  Host code never uses the symbol's name as an
 // address: hjcd_ctx_create looks up this device's copy once
@@ -140,6 +203,24 @@ size_t layout_staging_bytes(int32_t T) {
 }
 
 }  // namespace
+
+ObstacleGrid hjcd::scene_grid(const hjcd_scene_s* sc, const hjcd_robot_s* r) {
+    ObstacleGrid g{};
+    if (!sc || !sc->g_start || !r) return g;
+    float rmax = 0.f;
+    for (int l = 0; l <= r->n; ++l) rmax = std::max(rmax, r->host.coarse[l][3]);
+    // the cell a centre rounds into is at most a cell away from the true one
+    // (covered by the extra ring of cells); the radius must fit the margin
+    if (rmax > sc->g_margin - 1e-4f) return g;
+    g.start = sc->g_start;
+    g.items = sc->g_items;
+    for (int k = 0; k < 3; ++k) {
+        g.lo[k] = sc->g_lo[k];
+        g.n[k] = sc->g_n[k];
+    }
+    g.inv_h = 1.f / sc->g_h;
+    return g;
+}
 
 hjcd_status hjcd::check_params(const hjcd_params* p) {
     if (!p) return fail(HJCD_E_INVALID, "params is NULL");
@@ -576,6 +657,7 @@ hjcd_status hjcd_load_scene(hjcd_ctx c, int32_t n_sph, const float* sph, int32_t
     if (ok && n_box > 0) ok = ok && hipMalloc(&sc->box, sizeof(float) * 8 * n_box) == hipSuccess;
     if (ok && n_sph > 0) ok = hipMemcpy(sc->sph, sph, sizeof(float) * 4 * n_sph, hipMemcpyHostToDevice) == hipSuccess;
     if (ok && n_box > 0) ok = hipMemcpy(sc->box, bx.data(), sizeof(float) * 8 * n_box, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && n_sph + n_box >= kGridMinObstacles) ok = build_grid(sc, n_sph, sph, n_box, box);
     if (!ok) {
         hjcd_scene_destroy(sc);
         return fail(HJCD_E_NOMEM, "scene upload failed");
@@ -590,6 +672,8 @@ void hjcd_scene_destroy(hjcd_scene sc) {
     (void)hipDeviceSynchronize();
     if (sc->sph) (void)hipFree(sc->sph);
     if (sc->box) (void)hipFree(sc->box);
+    if (sc->g_start) (void)hipFree(sc->g_start);
+    if (sc->g_items) (void)hipFree(sc->g_items);
     delete sc;
 }
 
@@ -734,6 +818,7 @@ hjcd_status hjcd_collide(hjcd_ctx c, hjcd_robot r, hjcd_scene sc, int64_t S, con
     a.n_osph = sc ? sc->n_sph : 0;
     a.obox = sc ? sc->box : nullptr;
     a.n_obox = sc ? sc->n_box : 0;
+    a.grid = scene_grid(sc, r);
     a.flag = flag;
     a.counters = nullptr;
     HIP_TRY(launch_collide(a, (hipStream_t)stream));
@@ -1109,6 +1194,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
         a.n_osph = sc ? sc->n_sph : 0;
         a.obox = sc ? sc->box : nullptr;
         a.n_obox = sc ? sc->n_box : 0;
+        a.grid = scene_grid(sc, robots[ri]);
         a.flag = (uint8_t*)w_flag + base;
         a.counters = ss.counters();
         HIP_TRY(launch_collide(a, st));

@@ -83,4 +83,17 @@ struct hjcd_scene_s {
     int32_t n_sph = 0;
     float* box = nullptr;
     int32_t n_box = 0;
+    // obstacle grid (hjcd_launch.hpp ObstacleGrid), device arrays owned here
+    int32_t* g_start = nullptr;
+    int32_t* g_items = nullptr;
+    float g_lo[3] = {0.f, 0.f, 0.f};
+    float g_h = 0.f;
+    int32_t g_n[3] = {0, 0, 0};
+    float g_margin = 0.f;
 };
+
+namespace hjcd {
+// The scene's obstacle grid for a robot whose coarse link spheres all fit its
+// margin; an empty grid (flat obstacle loops) otherwise or without a scene.
+ObstacleGrid scene_grid(const hjcd_scene_s* sc, const hjcd_robot_s* r);
+}  // namespace hjcd

@@ -139,14 +139,81 @@ __device__ __forceinline__ void box_obstacle(const DevRobot* __restrict__ rb, co
     }
 }
 
+__device__ __forceinline__ int wave_max_i32(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// The obstacles of the grid cell holding this lane's coarse centre cc
+// (radius Rc <= the grid's margin) against the link's spheres f0 .. f0 + fc
+// - 1 (frame F): coarse test per listed obstacle, fine tests for the lanes
+// whose coarse test hit.  Every obstacle the flat loops would find touching
+// is listed, so the flag is the same.
+__device__ __forceinline__ void grid_obstacles(const DevRobot* __restrict__ rb, const ObstacleGrid& g, const Frame& F,
+                                               int f0, int fc, V3 cc, float Rc, const float* __restrict__ os,
+                                               int n_osph, const float* __restrict__ ob, bool& hit,
+                                               uint32_t& n_coarse, uint32_t& n_fine) {
+    int32_t c0 = 0, len = 0;
+    if (!hit) {
+        const int ix = (int)floorf((cc.x - g.lo[0]) * g.inv_h);
+        const int iy = (int)floorf((cc.y - g.lo[1]) * g.inv_h);
+        const int iz = (int)floorf((cc.z - g.lo[2]) * g.inv_h);
+        if (ix >= 0 && ix < g.n[0] && iy >= 0 && iy < g.n[1] && iz >= 0 && iz < g.n[2]) {
+            const int64_t cell = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
+            c0 = g.start[cell];
+            len = g.start[cell + 1] - c0;
+        }
+    }
+    const int steps = wave_max_i32(len);
+    for (int i = 0; i < steps; ++i) {
+        if (wave_all(hit)) break;
+        const bool has = !hit && i < len;
+        const int32_t o = has ? g.items[c0 + i] : 0;
+        const bool sphere = o < n_osph;
+        V3 co = mk(0.f, 0.f, 0.f);
+        float ro = 0.f;
+        const float* b = ob;
+        bool ch = false;
+        if (has) {
+            if (sphere) {
+                co = mk(os[4 * o], os[4 * o + 1], os[4 * o + 2]);
+                ro = os[4 * o + 3];
+                const V3 d = cc - co;
+                const float rr = Rc + ro;
+                ch = dot(d, d) < rr * rr;
+            } else {
+                b = ob + 8 * (o - n_osph);
+                ch = box_d2(cc, b) < Rc * Rc;
+            }
+        }
+        n_coarse += has ? 1u : 0u;
+        if (!wave_any(ch)) continue;
+        for (int k = 0; k < fc; ++k) {
+            const float* sp = rb->sph[f0 + k];
+            if (ch && !hit) {
+                const V3 c = xform(F, sp[0], sp[1], sp[2]);
+                ++n_fine;
+                if (sphere) {
+                    const V3 df = c - co;
+                    const float r2 = sp[3] + ro;
+                    if (dot(df, df) < r2 * r2) hit = true;
+                } else if (box_d2(c, b) < sp[3] * sp[3]) {
+                    hit = true;
+                }
+            }
+        }
+    }
+}
+
 // Collision test of one lane whose joint values are q[i * q_stride + s];
 // inactive lanes count as done so the wave can leave early.  Returns the
 // collision flag of an active lane.
 __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, int n, float* lds, int lane,
                                              bool active, const float* __restrict__ q, int64_t q_stride,
                                              int64_t s, const float* __restrict__ os, int n_osph,
-                                             const float* __restrict__ ob, int n_obox, uint32_t& n_coarse,
-                                             uint32_t& n_fine) {
+                                             const float* __restrict__ ob, int n_obox, const ObstacleGrid& g,
+                                             uint32_t& n_coarse, uint32_t& n_fine) {
     bool hit = !active;
     // environment, link by link along the chain walk (the frame is in
     // registers); every frame is kept in LDS for the self pairs
@@ -162,6 +229,10 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
         if (Rc < 0.f) continue;
         const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
         const int f0 = rb->link_first[l], fc = rb->link_count[l];
+        if (g.start) {
+            grid_obstacles(rb, g, F, f0, fc, cc, Rc, os, n_osph, ob, hit, n_coarse, n_fine);
+            continue;
+        }
         // Obstacles in groups of kObsGroup: the group's (uniform) loads and
         // coarse distances first, so the loads of a group are in flight
         // together, then the tests in obstacle order exactly as one at a time
@@ -253,7 +324,7 @@ __global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
     const bool live = s < a.S;
     uint32_t n_coarse = 0, n_fine = 0;
     const bool hit = collide_lane(a.rb, a.n, lds, lane, live, a.q, a.q_stride, s, a.osph, a.n_osph, a.obox,
-                                  a.n_obox, n_coarse, n_fine);
+                                  a.n_obox, a.grid, n_coarse, n_fine);
     if (live) a.flag[s] = hit ? 1 : 0;
     if (a.counters) {
         Counters c;
@@ -275,7 +346,7 @@ __global__ __launch_bounds__(64) void k_serve_check(ServeCheckArgs a) {
                       (a.all_lanes[e] || (st & SLOT_POL_FROZEN));
     uint32_t n_coarse = 0, n_fine = 0;
     const bool hit = collide_lane(a.rb, a.n, lds, lane, want, a.st.q, a.st.C, s, a.osph, a.n_osph, a.obox,
-                                  a.n_obox, n_coarse, n_fine);
+                                  a.n_obox, a.grid, n_coarse, n_fine);
     if (want) a.st.sstate[s] = (uint8_t)(st | SLOT_CHECKED | (hit ? SLOT_COLLIDES : 0));
 }
 

@@ -73,6 +73,23 @@ hipError_t launch_solve(const SolveArgs& a, hipStream_t st);
 hipError_t launch_fk(const DevRobot* rb, int n, int64_t S, const float* q, float* pose, float* jac,
                      hipStream_t st);
 
+// Uniform grid over a scene's obstacles (built by hjcd_load_scene for
+// scenes of kGridMinObstacles obstacles or more): cell (i, j, k) of size h
+// from corner lo lists, in [start[c], start[c + 1]) of items, every obstacle
+// (sphere index, or n_osph + box index) whose bounding box grown by the
+// grid's margin overlaps the cell.  A coarse sphere of radius <= margin whose
+// centre lies in a cell can only touch the obstacles that cell lists, and
+// none when its centre lies outside the grid.  start == nullptr: no grid
+// (flat loops over every obstacle).
+struct ObstacleGrid {
+    const int32_t* start;
+    const int32_t* items;
+    float lo[3];
+    float inv_h;
+    int32_t n[3];
+};
+constexpr int kGridMinObstacles = 96;
+
 struct CollideArgs {
     const DevRobot* rb;
     int32_t n;
@@ -85,6 +102,7 @@ struct CollideArgs {
     int32_t n_obox;
     uint8_t* flag;
     unsigned long long* counters;
+    ObstacleGrid grid;
 };
 
 hipError_t launch_collide(const CollideArgs& a, hipStream_t st);
@@ -197,6 +215,7 @@ struct ServeCheckArgs {
     int32_t n_osph;
     const float* obox;
     int32_t n_obox;
+    ObstacleGrid grid;
 };
 
 hipError_t launch_serve_check(const ServeCheckArgs& a, hipStream_t stream);

@@ -153,6 +153,7 @@ CollideArgs collide_args(hjcd_plan p, int ri) {
     a.n_osph = p->scene ? p->scene->n_sph : 0;
     a.obox = p->scene ? p->scene->box : nullptr;
     a.n_obox = p->scene ? p->scene->n_box : 0;
+    a.grid = scene_grid(p->scene, p->robots[ri]);
     a.flag = p->fl + base;
     a.counters = nullptr;
     return a;

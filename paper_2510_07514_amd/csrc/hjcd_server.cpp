@@ -346,6 +346,7 @@ hjcd_status batched_step(hjcd_server s) {
         ck.n_osph = s->scene ? s->scene->n_sph : 0;
         ck.obox = s->scene ? s->scene->box : nullptr;
         ck.n_obox = s->scene ? s->scene->n_box : 0;
+        ck.grid = scene_grid(s->scene, s->robot);
         HIP_TRY(launch_serve_check(ck, s->stream));
     }
     int32_t* h_status = (int32_t*)s->h_down;

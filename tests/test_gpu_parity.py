@@ -142,7 +142,7 @@ def test_collision_flags(H, ctx, which):
     fl = flag.cpu().numpy()
     rh, sh = O.RobotHandle(rob), O.SceneHandle(b.scene)
     checked = band = 0
-    for s in range(0, S, 3 if which != "large" else 11):
+    for s in range(0, S, 3 if which == "tiny" else 1):
         f, md = O.collide(rh, sh, q[s].astype(np.float64))
         if abs(md) < 1e-5:
             band += 1
@@ -151,6 +151,38 @@ def test_collision_flags(H, ctx, which):
         assert fl[s] == f, (s, md)
     say(f"  checked {checked}, in contact band {band}, colliding {fl.mean():.3f}")
     assert checked > 100
+
+
+def test_collision_grid_dense_scene(H, ctx):
+    """A cluttered scene (100 spheres and 100 boxes of 1-3 cm around the
+    Panda-like arm's workspace: the library lists obstacles per grid cell for
+    scenes of 96 obstacles or more) gives the oracle's flat all-pairs flags on
+    every configuration outside the contact band."""
+    import torch
+    say("case: collide, dense scene through the obstacle grid")
+    rob = W.config_batched(T=1, M=1).robots[0]
+    rng = np.random.default_rng(33)
+    scene = W.random_scene(rng, 100, 100, np.array([-1.0, -1.0, 0.0]), np.array([1.0, 1.0, 1.4]),
+                           r_range=(0.01, 0.03), half_range=(0.01, 0.03))
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, scene.spheres, scene.boxes)
+    S = 3000 + 17
+    q = W.uniform_configs(rng, rob, S)
+    flag = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    H.hjcd_collide(ctx, rb, sc, soa(q, rob.dof), flag)
+    _sync()
+    fl = flag.cpu().numpy()
+    rh, sh = O.RobotHandle(rob), O.SceneHandle(scene)
+    checked = band = 0
+    for s in range(S):
+        f, md = O.collide(rh, sh, q[s].astype(np.float64))
+        if abs(md) < 1e-5:
+            band += 1
+            continue
+        checked += 1
+        assert fl[s] == f, (s, md)
+    say(f"  checked {checked}, in contact band {band}, colliding {fl.mean():.3f}")
+    assert checked > 2900 and 0.1 < fl.mean() < 0.95
 
 
 # ---------------------------------------------------------------------------
