@@ -1119,17 +1119,139 @@ __device__ __forceinline__ void line_search_spread(RobotRef rb, int n, const Tar
 }
 
 // ----------------------------------------------------------------------------
+// The same spread line search with the searching lanes' records staged in LDS.
+//
+// Each lane the alpha = 1 trial did not satisfy writes its joint values, step
+// and target to slot r (its rank among those lanes) of the wave's own LDS
+// records, structure-of-arrays by field so that a pass reads and writes
+// consecutive words.  Task t = (i - 1) nneed + r evaluates trial i of slot r
+// and stores its cost at [i - 1][r]; each searching lane then reads its A
+// costs, takes the first below c0 and rebuilds that trial (its step read back
+// from the records).  Only this wave's lanes touch its records, so no
+// workgroup barrier is needed.  Values and choices are those of the
+// sequential search.
+// ----------------------------------------------------------------------------
+template <int NM>
+__host__ __device__ constexpr int ls_wave_floats() {
+    return (2 * NM + 7 + kLsSpread) * 64;
+}
+
+// Order this wave's LDS accesses (in-order execution within a wave; this
+// keeps the compiler from moving loads and stores across it).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NM>
+__device__ __forceinline__ void line_search_lds(RobotRef rb, int n, const Target& tg, const KParams& kp, float* th,
+                                                const float* dth, float* tt, float c0, bool& done, Counters& cnt,
+                                                float* __restrict__ ws) {
+    if (!wave_all(done)) {
+        if (!done) {
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) tt[j] = clampf(fmaf(1.f, dth[j], th[j]), rb->lo[j], rb->hi[j]);
+            const float c1 = trial_cost<NM>(rb, n, tg, tt);
+            ++cnt.pol_trials;
+            if (c1 < c0) {
+#pragma unroll
+                for (int j = 0; j < NM; ++j)
+                    if (j < n) th[j] = tt[j];
+                done = true;
+            }
+        }
+    }
+    const int A = kp.ls_A;
+    const uint64_t need = __ballot(!done);
+    if (A == 0 || need == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int nneed = __popcll(need);
+    const int ntask = nneed * A;
+    const int myrank = __popcll(need & ((1ull << lane) - 1ull));
+    float* __restrict__ wth = ws;                     // [NM][64] by rank
+    float* __restrict__ wdt = ws + NM * 64;           // [NM][64] by rank
+    float* __restrict__ wtg = ws + 2 * NM * 64;       // [7][64] by rank
+    float* __restrict__ wc = ws + (2 * NM + 7) * 64;  // [A][64] by rank
+    if (!done) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            if (j < n) {
+                wth[j * 64 + myrank] = th[j];
+                wdt[j * 64 + myrank] = dth[j];
+            }
+        }
+        wtg[0 * 64 + myrank] = tg.p.x;
+        wtg[1 * 64 + myrank] = tg.p.y;
+        wtg[2 * 64 + myrank] = tg.p.z;
+        wtg[3 * 64 + myrank] = tg.q.w;
+        wtg[4 * 64 + myrank] = tg.q.x;
+        wtg[5 * 64 + myrank] = tg.q.y;
+        wtg[6 * 64 + myrank] = tg.q.z;
+    }
+    wave_lds_sync();
+    // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 512,
+    // so its FP32 product with the rounded reciprocal floors exactly
+    const float inv_need = 1.f / (float)nneed;
+    for (int base = 0; base < ntask; base += 64) {
+        const int t = base + lane;
+        if (t < ntask) {
+            const int im1 = (int)(((float)t + 0.5f) * inv_need);  // trial index - 1
+            const int r = t - im1 * nneed;
+            float a = 1.f;
+#pragma unroll
+            for (int k = 1; k <= kLsSpread; ++k)
+                if (k <= im1 + 1) a *= kp.inv_beta;
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) tt[j] = clampf(fmaf(a, wdt[j * 64 + r], wth[j * 64 + r]), rb->lo[j], rb->hi[j]);
+            Target tgL;
+            tgL.p = mk(wtg[0 * 64 + r], wtg[1 * 64 + r], wtg[2 * 64 + r]);
+            tgL.q = Quat{wtg[3 * 64 + r], wtg[4 * 64 + r], wtg[5 * 64 + r], wtg[6 * 64 + r]};
+            wc[im1 * 64 + r] = trial_cost<NM>(rb, n, tgL, tt);
+        }
+    }
+    wave_lds_sync();
+    if (!done) {
+        int first = -1;
+#pragma unroll
+        for (int k = kLsSpread - 1; k >= 0; --k)
+            if (k < A && wc[k * 64 + myrank] < c0) first = k;
+        cnt.pol_trials += first >= 0 ? (uint32_t)(first + 1) : (uint32_t)A;
+        if (first >= 0) {
+            float a = 1.f;
+#pragma unroll
+            for (int k = 1; k <= kLsSpread; ++k)
+                if (k <= first + 1) a *= kp.inv_beta;
+#pragma unroll
+            for (int j = 0; j < NM; ++j)
+                if (j < n) th[j] = clampf(fmaf(a, wdt[j * 64 + myrank], th[j]), rb->lo[j], rb->hi[j]);
+            done = true;
+        }
+    }
+    wave_lds_sync();  // the records are free for the next iteration's writes
+}
+
+// Line-search forms of pj_ik_iter: sequential, spread over the wave through
+// shuffles, spread through the wave's LDS records.
+constexpr int kLsSeq = 0;
+constexpr int kLsShfl = 1;
+constexpr int kLsLds = 2;
+
+// ----------------------------------------------------------------------------
 // One PJ-IK iteration (Alg. PJ-IK, Sec. IV-B), number `it`, on one seed per
-// lane.  SPREAD selects the spread line search above (same results; fewer
-// passes, more live registers).
+// lane.  LS selects the line-search form above (same results): the spread
+// forms run fewer passes; the shuffle form needs more live registers, the
+// LDS form needs ls_wave_floats<NM>() floats of LDS per wave at `lsw`.
 // LM step: (J^T W^2 J + lam D) dtheta = J^T W^2 e is solved in its 6 x 6
 // push-through form dtheta = D^-1 J^T W (W J D^-1 J^T W + lam I)^-1 W e.
 // ----------------------------------------------------------------------------
-template <int NM, bool SPREAD = true>
+template <int NM, int LS = kLsShfl>
 __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg, const KParams& kp,
                                            uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
                                            Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int it,
-                                           float& last_ep, float& last_phi) {
+                                           float& last_ep, float& last_phi, float* __restrict__ lsw = nullptr) {
     V3 Jp[NM], Z[NM];
     float dth[NM], tt[NM];
     const float R = kp.trust_R;
@@ -1231,7 +1353,9 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
             write_traj<NM>(traj, n, S, s, it, th, last_ep, last_phi);
         }
         // --- backtracking line search (eq. line-search), first decreasing alpha
-        if (SPREAD && kp.ls_A <= kLsSpread) {
+        if (LS == kLsLds && kp.ls_A <= kLsSpread) {
+            line_search_lds<NM>(rb, n, tg, kp, th, dth, tt, c0, done, cnt, lsw);
+        } else if (LS == kLsShfl && kp.ls_A <= kLsSpread) {
             line_search_spread<NM>(rb, n, tg, kp, th, dth, tt, c0, done, cnt);
         } else {
             float alpha = 1.f;
@@ -1446,15 +1570,15 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
 
 // Iterations [k0, k1) of PJ-IK on one seed per lane; out_err is the residual
 // at the configuration the last iteration produced (when want_err).
-template <int NM, bool SPREAD = true>
+template <int NM, int LS = kLsShfl>
 __device__ __forceinline__ void pj_ik(RobotRef rb, int n, const Target& tg, const KParams& kp,
                                       uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
                                       Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
-                                      int k1, Err& out_err, bool want_err = true) {
+                                      int k1, Err& out_err, bool want_err = true, float* __restrict__ lsw = nullptr) {
     float last_ep = 0.f, last_phi = 0.f;
     for (int it = k0; it < k1; ++it) {
         if (wave_all(frozen) && !traj) break;
-        pj_ik_iter<NM, SPREAD>(rb, n, tg, kp, m, tkey, th, live, frozen, cnt, traj, S, s, it, last_ep, last_phi);
+        pj_ik_iter<NM, LS>(rb, n, tg, kp, m, tkey, th, live, frozen, cnt, traj, S, s, it, last_ep, last_phi, lsw);
     }
     if (!want_err) return;  // the caller continues this seed in a later call
     Frame ee;

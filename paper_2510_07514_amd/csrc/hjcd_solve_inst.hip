@@ -28,11 +28,32 @@ constexpr bool kExactN = HJCD_NM < 8;
 template <int NM, int V>
 struct SolveOcc {
     static constexpr int waves = NM <= 8 ? (V == 0 ? 3 : 2) : NM <= 16 ? (V == 0 ? 2 : 1) : (V == 0 ? 1 : 2);
-    // the spread line search needs ~50 more live registers: at three waves per
-    // SIMD they would spill, so buckets up to 8 joints keep the sequential
-    // search in both variants
-    static constexpr bool spread = NM > 8;
+    // line-search form (same results): the shuffle form needs ~50 more live
+    // registers, which would spill at three waves per SIMD, so up to 8 joints
+    // the searching lanes' records go through LDS; so too at 24 joints, where
+    // it halves PJ-IK's spills at two waves (188 -> 99 registers; 24-joint
+    // chain, 2,000 x 256: 5.11 -> 3.81 ms).  At 32 joints (one wave, no
+    // spills) the shuffles measured faster (3.93 vs 4.09 ms), at 12 and 20
+    // joints the two are within 1-2%.
+    static constexpr int ls = (NM <= 8 || NM == 24) ? kLsLds : kLsShfl;
 };
+
+// LDS of the line-search records of a workgroup of `threads` threads.
+template <int NM, int LS>
+constexpr size_t ls_lds_bytes(int threads) {
+    return LS == kLsLds ? (size_t)(threads / 64) * ls_wave_floats<NM>() * sizeof(float) : 0;
+}
+
+// This wave's records in the workgroup's dynamic LDS (LDS line-search form).
+template <int NM, int LS>
+__device__ __forceinline__ float* ls_records() {
+    if constexpr (LS == kLsLds) {
+        extern __shared__ float ls_dyn[];
+        return ls_dyn + (threadIdx.x >> 6) * ls_wave_floats<NM>();
+    } else {
+        return nullptr;
+    }
+}
 
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
@@ -65,7 +86,7 @@ __device__ __forceinline__ void write_seed(const SolveArgs& a, int n, const floa
     if (a.cost) a.cost[s] = cost_of(e);
 }
 
-template <int NM, bool SPREAD>
+template <int NM, int LS>
 __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool do_polish) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
@@ -92,8 +113,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     }
     if (do_polish) {
         bool frozen = !live;
-        pj_ik<NM, SPREAD>(robot_ref(a.rb), n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt,
-                          do_cd ? nullptr : a.traj, a.S, sl.s, 0, a.kp.polish_iters, e);
+        pj_ik<NM, LS>(robot_ref(a.rb), n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt,
+                      do_cd ? nullptr : a.traj, a.S, sl.s, 0, a.kp.polish_iters, e, true, ls_records<NM, LS>());
     }
     if (!do_cd && !do_polish && a.targets) {
         Frame ee;
@@ -112,7 +133,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
 // range lasts instead of idling once their seed has converged.  A seed's
 // iterations, keys and arithmetic do not depend on its lane or on when it
 // starts, so the results equal those of one seed per lane.
-template <int NM, bool SPREAD>
+template <int NM, int LS>
 __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t P = a.seeds_per_wave;
@@ -154,8 +175,8 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
         const bool run = has && !frozen && it < K;
         if (wave_any(run)) {
             bool fz = !run;
-            pj_ik_iter<NM, SPREAD>(rb, n, tg, a.kp, sl.m, sl.tkey, th, false, fz, cnt, nullptr, a.S, sl.s, it,
-                                   last_ep, last_phi);
+            pj_ik_iter<NM, LS>(rb, n, tg, a.kp, sl.m, sl.tkey, th, false, fz, cnt, nullptr, a.S, sl.s, it,
+                               last_ep, last_phi, ls_records<NM, LS>());
             if (run) {
                 frozen = fz;
                 ++it;
@@ -185,7 +206,7 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
 template <int NM, int V>
 struct PolishOcc {
     static constexpr int waves = (NM > 16 && NM <= 24) ? (V == 0 ? 2 : 1) : SolveOcc<NM, V>::waves;
-    static constexpr bool spread = SolveOcc<NM, V>::spread;
+    static constexpr int ls = SolveOcc<NM, V>::ls;
 };
 template <int NM>
 struct CdOcc {
@@ -233,27 +254,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::
 // Seed initialisation only (hjcd_init_seeds): uniform draws written out.
 template <int NM>
 __global__ __launch_bounds__(256) void k_seed(SolveArgs a) {
-    solve_body<NM, false>(a, false, false);
+    solve_body<NM, kLsSeq>(a, false, false);
 }
 
 // PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
 // kernel compiled for its stage alone.
 template <int NM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::waves))) void k_cd(SolveArgs a) {
-    solve_body<NM, false>(a, true, false);
+    solve_body<NM, kLsSeq>(a, true, false);
 }
 
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish(
     SolveArgs a) {
-    solve_body<NM, PolishOcc<NM, V>::spread>(a, false, true);
+    solve_body<NM, PolishOcc<NM, V>::ls>(a, false, true);
 }
 
 // PJ-IK only, streaming seeds through the waves (large launches).
 template <int NM, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish_stream(
     SolveArgs a) {
-    polish_stream<NM, PolishOcc<NM, V>::spread>(a);
+    polish_stream<NM, PolishOcc<NM, V>::ls>(a);
 }
 
 // ----------------------------------------------------------------------------
@@ -293,8 +314,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
         if (frozen) st |= SLOT_CD_FROZEN;
     } else {
         bool frozen = !live || (st & SLOT_POL_FROZEN);
-        pj_ik<NM, SolveOcc<NM, 0>::spread>(robot_ref(a.rb), n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0,
-                                          blk.k1, er);
+        constexpr int LS = SolveOcc<NM, 0>::ls;
+        __shared__ float ls_rec[LS == kLsLds ? 4 * ls_wave_floats<NM>() : 1];
+        pj_ik<NM, LS>(robot_ref(a.rb), n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er,
+                      true, LS == kLsLds ? ls_rec + (threadIdx.x >> 6) * ls_wave_floats<NM>() : nullptr);
         // the exit test of iteration k1 (or the one after the last iteration)
         // on the state this chunk leaves: a seed converged by the chunk's last
         // step is eligible for the collision check at this chunk's end
@@ -329,6 +352,7 @@ hipError_t launch_solve_nm(const SolveArgs& a, hipStream_t st);
 template <>
 hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     const int bt = a.block_threads > 0 ? a.block_threads : 256;
+    if (bt % 64 != 0 || bt > 256) return hipErrorInvalidValue;  // whole waves; launch bound 256
     const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
     if (a.do_cd && a.do_polish) return hipErrorInvalidValue;  // the stages run as separate launches
     // PJ-IK streams seeds through its waves once the launch holds enough
@@ -342,6 +366,8 @@ hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     ps.seeds_per_wave = 64 * sf;
     const int64_t seeds_per_block = ps.seeds_per_wave * (bt / 64);
     const unsigned nbp = (unsigned)((a.map.Sv + seeds_per_block - 1) / seeds_per_block);
+    const size_t lds0 = ls_lds_bytes<HJCD_NM, PolishOcc<HJCD_NM, 0>::ls>(bt);  // line-search records
+    const size_t lds1 = ls_lds_bytes<HJCD_NM, PolishOcc<HJCD_NM, 1>::ls>(bt);
     bool pair_cd = false;
     if constexpr (kPairCd) pair_cd = a.do_cd && a.cd_lanes == 2;  // smaller buckets keep one lane
     if (pair_cd) {
@@ -354,13 +380,13 @@ hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     else if (!a.do_polish)
         hipLaunchKernelGGL((k_seed<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
     else if (sf > 1 && a.variant == 1)
-        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1>), dim3(nbp), dim3(bt), 0, st, ps);
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1>), dim3(nbp), dim3(bt), lds1, st, ps);
     else if (sf > 1)
-        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0>), dim3(nbp), dim3(bt), 0, st, ps);
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0>), dim3(nbp), dim3(bt), lds0, st, ps);
     else if (a.variant == 1)
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), lds1, st, a);
     else
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), lds0, st, a);
     return hipGetLastError();
 }
 
