@@ -166,10 +166,14 @@ def measure(H, ctx, torch, batch, steps, warmup):
         fl = torch.zeros(T * k, dtype=torch.uint8, device=dev)
         nf = torch.zeros(T, dtype=torch.int32, device=dev)
         sv = torch.zeros(T, dtype=torch.uint8, device=dev)
-    p = H.params_from_dict(batch.params, collect_stats=True)
+    # timed steps: stage times only (the kernels a caller without statistics runs);
+    # the executed-work counts come from one more solve with counters, whose
+    # results are the same bit for bit
+    p = H.params_from_dict(batch.params, collect_stats=2)
+    p_count = H.params_from_dict(batch.params, collect_stats=1)
 
-    def step():
-        H.hjcd_solve(ctx, [rb], sc, targets, batch.seed_offsets, p, q_out, ep, eo, fl, nf, sv, stream=stream)
+    def step(params=p):
+        H.hjcd_solve(ctx, [rb], sc, targets, batch.seed_offsets, params, q_out, ep, eo, fl, nf, sv, stream=stream)
 
     for _ in range(warmup):
         step()
@@ -194,6 +198,11 @@ def measure(H, ctx, torch, batch, steps, warmup):
     best_eo = eo.view(T, k)[:, 0].cpu().numpy()
     ms_per_step = wall * 1e3 / steps
     per_step = {kk: v / steps for kk, v in agg.items()}
+    q_timed = q_out.clone()
+    step(p_count)
+    counts = H.hjcd_get_stats(ctx)
+    if not torch.equal(q_out, q_timed):
+        raise RuntimeError("the solve with counters returned other configurations than the timed solves")
     rb.close()
     sc.close()
     return {"value": round(n_solved / (ms_per_step / 1e3), 1), "ms_per_step": round(ms_per_step, 3),
@@ -203,7 +212,7 @@ def measure(H, ctx, torch, batch, steps, warmup):
                            "p99": round(float(np.percentile(step_ms, 99)), 3)},
             "stage_ms": {kk: round(per_step[kk], 4) for kk in
                          ("ms_cd", "ms_resample", "ms_polish", "ms_collide", "ms_select", "ms_total")},
-            "work_per_step": {kk: int(per_step[kk]) for kk in
+            "work_per_step": {kk: int(counts[kk]) for kk in
                               ("seeds", "cd_iters", "cd_perturb", "pol_iters", "pol_trials", "pol_dogleg",
                                "pol_single", "pol_perturb", "coll_coarse", "coll_fine")}}
 

@@ -119,7 +119,9 @@ typedef struct {
     int32_t top_k;           /* solutions returned per target, 1..HJCD_MAX_TOPK */
     float succ_pos, succ_ori;/* success: collision free and |r_p| <= succ_pos, phi <= succ_ori */
     uint64_t rng_seed;       /* Philox key */
-    int32_t collect_stats;   /* 1: time each kernel and count executed work (hjcd_get_stats) */
+    int32_t collect_stats;   /* 0: none; 1: time each kernel and count executed work (the per-seed
+                                kernels then run a build with counters); 2: time each kernel only
+                                (the kernels of collect_stats = 0, counts read 0); hjcd_get_stats */
     int32_t polish_variant;  /* launch shape of the PJ-IK kernel: 0 default, 1 the other occupancy
                                 (waves per SIMD 3 / 2 up to 8 joints, 2 / 1 up to 24, 1 / 2 above);
                                 the arithmetic is the same, so results are bit-identical */
@@ -129,9 +131,10 @@ typedef struct {
 } hjcd_params;
 
 /* Per-call measurements of the last hjcd_solve / stage call made with
- * collect_stats = 1 on a context.  Stage times are HIP-event intervals on the
- * call's stream: hjcd_solve reports its PO-CCD kernels in ms_cd and its PJ-IK
- * kernels in ms_polish (with resampling, the replication in ms_resample). */
+ * collect_stats = 1 or 2 on a context (work counts with 1 only).  Stage times
+ * are HIP-event intervals on the call's stream: hjcd_solve reports its PO-CCD
+ * kernels in ms_cd and its PJ-IK kernels in ms_polish (with resampling, the
+ * replication in ms_resample). */
 typedef struct {
     float ms_init, ms_cd, ms_resample, ms_polish, ms_collide, ms_select;
     float ms_total;          /* first to last event of the call */
@@ -299,8 +302,8 @@ hjcd_status hjcd_solve_near(hjcd_ctx ctx, int32_t n_robots, const hjcd_robot* ro
                             float* err_p, float* err_o, uint8_t* flag, int32_t* n_free, uint8_t* solved,
                             void* stream);
 
-/* Measurements of the last call made with collect_stats = 1 (synchronises
- * the stream that call used). */
+/* Measurements of the last call made with collect_stats = 1 or 2
+ * (synchronises the stream that call used). */
 hjcd_status hjcd_get_stats(hjcd_ctx ctx, hjcd_stats* out);
 
 /* ---- reusable plans (uneven batches) -----------------------------------------

@@ -244,6 +244,7 @@ hjcd_status hjcd::check_params(const hjcd_params* p) {
     if (p->resample_K < 0 || (p->resample_K > 0 && p->resample_B < p->resample_K))
         return fail(HJCD_E_INVALID, "resample needs K >= 0 and B >= K");
     if (p->polish_variant != 0 && p->polish_variant != 1) return fail(HJCD_E_INVALID, "polish_variant must be 0 or 1");
+    if (p->collect_stats < 0 || p->collect_stats > 2) return fail(HJCD_E_INVALID, "collect_stats must be 0, 1 or 2");
     if (p->cd_lanes_per_seed < 0 || p->cd_lanes_per_seed > 2)
         return fail(HJCD_E_INVALID, "cd_lanes_per_seed must be 0, 1 or 2");
     return HJCD_OK;
@@ -341,9 +342,11 @@ enum StatStage { SS_INIT = 0, SS_CD, SS_RESAMPLE, SS_POLISH, SS_COLLIDE, SS_SELE
 struct StatScope {
     hjcd_ctx c;
     hipStream_t st;
-    bool on;
-    hjcd_status begin(bool enabled, int64_t seeds) {
-        on = enabled;
+    bool on;     // stage times
+    bool count;  // executed-work counters (the kernels built with them)
+    hjcd_status begin(int32_t mode, int64_t seeds) {
+        on = mode != 0;
+        count = mode == 1;
         if (!on) return HJCD_OK;
         c->ev_used = 0;
         c->stats = hjcd_stats{};
@@ -361,7 +364,7 @@ struct StatScope {
         HIP_TRY(hipEventRecord(c->ev[c->ev_used++], st));
         return HJCD_OK;
     }
-    unsigned long long* counters() const { return on ? (unsigned long long*)c->counters.p : nullptr; }
+    unsigned long long* counters() const { return count ? (unsigned long long*)c->counters.p : nullptr; }
     void end() {
         if (on) c->stats_pending = true;
     }
@@ -758,7 +761,7 @@ static hjcd_status stage_common(hjcd_ctx c, hjcd_robot r, int32_t T, const float
     if ((s = bind(c)) != HJCD_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     StatScope ss{c, st, false};
-    if ((s = ss.begin(p->collect_stats != 0, S)) != HJCD_OK) return s;
+    if ((s = ss.begin(p->collect_stats, S)) != HJCD_OK) return s;
     if ((s = upload_offsets(c, T, offs, st)) != HJCD_OK) return s;
     SolveArgs a{};
     a.rb = r->dev;
@@ -1041,7 +1044,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
                         off, (size_t)HJCD_NOALLOC_SCRATCH_BYTES);
     }
     StatScope ss{c, st, false};
-    if ((s = ss.begin(p->collect_stats != 0, S)) != HJCD_OK) return s;
+    if ((s = ss.begin(p->collect_stats, S)) != HJCD_OK) return s;
     {
         Staging sg{c, st, !noalloc};
         if ((s = sg.begin(layout_staging_bytes(T))) != HJCD_OK) return s;

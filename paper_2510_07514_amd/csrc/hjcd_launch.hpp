@@ -197,7 +197,6 @@ struct ServeChunkArgs {
     const ServeBlock* blocks;  // [nb]
     int32_t nb;
     KernelParams kp;
-    unsigned long long* counters;
 };
 
 hipError_t launch_serve_chunk(const ServeChunkArgs& a, hipStream_t stream);

@@ -332,7 +332,6 @@ hjcd_status batched_step(hjcd_server s) {
     ca.blocks = d_blk;
     ca.nb = nb;
     ca.kp = kparams(p);
-    ca.counters = nullptr;
     HIP_TRY(launch_serve_chunk(ca, s->stream));
     if (nchk > 0) {
         ServeCheckArgs ck{};

@@ -86,7 +86,9 @@ __device__ __forceinline__ void write_seed(const SolveArgs& a, int n, const floa
     if (a.cost) a.cost[s] = cost_of(e);
 }
 
-template <int NM, int LS>
+// STATS: the kernel counts executed work into a.counters; without it the
+// counters are dead code and hold no registers (launches with no counters).
+template <int NM, int LS, bool STATS>
 __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool do_polish) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = v < a.map.Sv;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
         e = residual(ee, tg);
     }
     if (live) write_seed<NM>(a, n, th, e, sl.s);
-    flush_counters(cnt, a.counters, a.counters != nullptr);
+    flush_counters(cnt, a.counters, STATS && a.counters != nullptr);
 }
 
 // PJ-IK with seed streaming.  Wave w owns the seeds [w P, (w + 1) P) of the
@@ -133,7 +135,7 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
 // range lasts instead of idling once their seed has converged.  A seed's
 // iterations, keys and arithmetic do not depend on its lane or on when it
 // starts, so the results equal those of one seed per lane.
-template <int NM, int LS>
+template <int NM, int LS, bool STATS>
 __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
     const int lane = (int)(threadIdx.x & 63u);
     const int64_t P = a.seeds_per_wave;
@@ -192,7 +194,7 @@ __device__ __forceinline__ void polish_stream(const SolveArgs& a) {
             frozen = true;
         }
     }
-    flush_counters(cnt, a.counters, a.counters != nullptr);
+    flush_counters(cnt, a.counters, STATS && a.counters != nullptr);
 }
 
 // Occupancy of the single-stage kernels.  In the 20- and 24-joint buckets two
@@ -222,7 +224,7 @@ struct CdOcc {
 // lane 2v and 2v + 1 share seed v; the even lane writes the result.
 constexpr bool kPairCd = HJCD_NM >= 12;
 
-template <int NM>
+template <int NM, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::pair_waves))) void k_cd_pair(
     SolveArgs a) {
     const int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
@@ -248,33 +250,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::
     po_ccd_pair<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s, 0,
                     a.kp.cd_sweeps, e);
     if (live && even) write_seed<NM>(a, n, th, e, sl.s);
-    flush_counters(cnt, a.counters, a.counters != nullptr);
+    flush_counters(cnt, a.counters, STATS && a.counters != nullptr);
 }
 
 // Seed initialisation only (hjcd_init_seeds): uniform draws written out.
 template <int NM>
 __global__ __launch_bounds__(256) void k_seed(SolveArgs a) {
-    solve_body<NM, kLsSeq>(a, false, false);
+    solve_body<NM, kLsSeq, false>(a, false, false);
 }
 
 // PO-CCD only, and PJ-IK only: the whole solve runs them as two launches, each
 // kernel compiled for its stage alone.
-template <int NM>
+template <int NM, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CdOcc<NM>::waves))) void k_cd(SolveArgs a) {
-    solve_body<NM, kLsSeq>(a, true, false);
+    solve_body<NM, kLsSeq, STATS>(a, true, false);
 }
 
-template <int NM, int V>
+template <int NM, int V, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish(
     SolveArgs a) {
-    solve_body<NM, PolishOcc<NM, V>::ls>(a, false, true);
+    solve_body<NM, PolishOcc<NM, V>::ls, STATS>(a, false, true);
 }
 
 // PJ-IK only, streaming seeds through the waves (large launches).
-template <int NM, int V>
+template <int NM, int V, bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PolishOcc<NM, V>::waves))) void k_polish_stream(
     SolveArgs a) {
-    polish_stream<NM, PolishOcc<NM, V>::ls>(a);
+    polish_stream<NM, PolishOcc<NM, V>::ls, STATS>(a);
 }
 
 // ----------------------------------------------------------------------------
@@ -333,7 +335,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
         a.st.cost[s] = cost_of(er);
         a.st.sstate[s] = st;
     }
-    flush_counters(cnt, a.counters, a.counters != nullptr);
+    // the serving loop counts no executed work: cnt is dead code here
 }
 
 template <int NM>
@@ -349,8 +351,10 @@ hipError_t launch_serve_chunk_nm<HJCD_NM>(const ServeChunkArgs& a, hipStream_t s
 template <int NM>
 hipError_t launch_solve_nm(const SolveArgs& a, hipStream_t st);
 
-template <>
-hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
+// Templated on the bucket and file-local: every bucket's translation unit
+// defines its own (one shared name would let the linker keep a single body).
+template <int NM, bool STATS>
+static hipError_t launch_solve_stats(const SolveArgs& a, hipStream_t st) {
     const int bt = a.block_threads > 0 ? a.block_threads : 256;
     if (bt % 64 != 0 || bt > 256) return hipErrorInvalidValue;  // whole waves; launch bound 256
     const unsigned nb = (unsigned)((a.map.Sv + bt - 1) / bt);
@@ -373,21 +377,36 @@ hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
     if (pair_cd) {
         if constexpr (kPairCd) {
             const unsigned nb2 = (unsigned)((2 * a.map.Sv + bt - 1) / bt);
-            hipLaunchKernelGGL((k_cd_pair<HJCD_NM>), dim3(nb2), dim3(bt), 0, st, a);
+            hipLaunchKernelGGL((k_cd_pair<HJCD_NM, STATS>), dim3(nb2), dim3(bt), 0, st, a);
         }
     } else if (a.do_cd)
-        hipLaunchKernelGGL((k_cd<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_cd<HJCD_NM, STATS>), dim3(nb), dim3(bt), 0, st, a);
     else if (!a.do_polish)
         hipLaunchKernelGGL((k_seed<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
     else if (sf > 1 && a.variant == 1)
-        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1>), dim3(nbp), dim3(bt), lds1, st, ps);
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 1, STATS>), dim3(nbp), dim3(bt), lds1, st, ps);
     else if (sf > 1)
-        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0>), dim3(nbp), dim3(bt), lds0, st, ps);
+        hipLaunchKernelGGL((k_polish_stream<HJCD_NM, 0, STATS>), dim3(nbp), dim3(bt), lds0, st, ps);
     else if (a.variant == 1)
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 1>), dim3(nb), dim3(bt), lds1, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 1, STATS>), dim3(nb), dim3(bt), lds1, st, a);
     else
-        hipLaunchKernelGGL((k_polish<HJCD_NM, 0>), dim3(nb), dim3(bt), lds0, st, a);
+        hipLaunchKernelGGL((k_polish<HJCD_NM, 0, STATS>), dim3(nb), dim3(bt), lds0, st, a);
     return hipGetLastError();
+}
+
+// Launches that count executed work run the kernels compiled with counters;
+// the others run the builds without them (7 joints: PJ-IK 3.13 -> 3.03 ms,
+// spills 10 -> 2 registers; 24 joints 3.78 -> 3.60 ms), except at 20 joints,
+// where the build without counters places its spills worse and measured
+// 1-3% slower (both builds skip the counting when a.counters is null).
+constexpr bool kCounterFreeBuild = HJCD_NM != 20;
+
+template <>
+hipError_t launch_solve_nm<HJCD_NM>(const SolveArgs& a, hipStream_t st) {
+    if constexpr (kCounterFreeBuild) {
+        if (!a.counters) return launch_solve_stats<HJCD_NM, false>(a, st);
+    }
+    return launch_solve_stats<HJCD_NM, true>(a, st);
 }
 
 }  // namespace hjcd

@@ -270,14 +270,15 @@ def hjcd_params_default(**over) -> hjcd_params:
     return p
 
 
-def params_from_dict(d: dict, collect_stats: bool = False) -> hjcd_params:
-    """hjcd_params from the workload module's parameter dict."""
+def params_from_dict(d: dict, collect_stats: int = 0) -> hjcd_params:
+    """hjcd_params from the workload module's parameter dict (collect_stats:
+    0 / False none, 1 / True stage times and work counts, 2 stage times)."""
     p = hjcd_params_default()
     for k, v in d.items():
         name = "lambda_" if k == "lam" else k
         if any(f == name for f, _ in hjcd_params._fields_):
             setattr(p, name, v)
-    p.collect_stats = 1 if collect_stats else 0
+    p.collect_stats = int(collect_stats)
     return p
 
 

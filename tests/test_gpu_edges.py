@@ -185,3 +185,47 @@ def test_bitwise_repeatable(H, ctx):
     for r in runs[1:]:
         for key in ("q", "ep", "eo", "fl", "nf", "sv"):
             assert np.array_equal(runs[0][key], r[key]), key
+
+
+@pytest.mark.parametrize("robot", ["panda", "random24"])
+def test_statistics_modes_bit_identical(H, ctx, robot):
+    """collect_stats 0 (no statistics), 1 (stage times and work counts: the
+    per-seed kernels built with counters) and 2 (stage times only) return the
+    same outputs bit for bit; counts are reported in mode 1 only."""
+    import torch
+    say(f"case: statistics modes, {robot}")
+    if robot == "panda":
+        b = W.config_batched(T=64, M=1024)
+        rob, scene, params, offs = b.robots[0], b.scene, b.params, b.seed_offsets
+        tg = O.targets_from_qstar(rob, b.q_star)
+    else:
+        rob = W.random_chain(np.random.default_rng(24), 24)
+        scene = W.config_batched(T=1, M=1).scene
+        params = W.default_params(top_k=4)
+        T = 32
+        tg = O.targets_from_qstar(rob, W.uniform_configs(np.random.default_rng(3), rob, T))
+        offs = np.arange(T + 1, dtype=np.int64) * 512
+    T, k, n = len(tg), params["top_k"], rob.dof
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, scene.spheres, scene.boxes)
+    targets = torch.as_tensor(np.ascontiguousarray(np.asarray(tg, np.float32).reshape(-1, 7).T)).cuda()
+    outs, stats = [], []
+    for mode in (0, 1, 2):
+        o = [torch.zeros(T * k, n, device="cuda"), torch.zeros(T * k, device="cuda"), torch.zeros(T * k, device="cuda"),
+             torch.zeros(T * k, dtype=torch.uint8, device="cuda"), torch.zeros(T, dtype=torch.int32, device="cuda"),
+             torch.zeros(T, dtype=torch.uint8, device="cuda")]
+        H.hjcd_solve(ctx, [rb], sc, targets, offs, H.params_from_dict(params, collect_stats=mode), *o)
+        stats.append(H.hjcd_get_stats(ctx) if mode else None)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in o])
+    rb.close()
+    sc.close()
+    for r in outs[1:]:
+        for a, c in zip(outs[0], r):
+            assert np.array_equal(a, c)
+    s1, s2 = stats[1], stats[2]
+    say(f"  mode 1: ms_polish {s1['ms_polish']:.3f} pol_iters {s1['pol_iters']}; mode 2: ms_polish "
+        f"{s2['ms_polish']:.3f} pol_iters {s2['pol_iters']}")
+    assert s1["pol_iters"] > 0 and s1["cd_iters"] > 0 and s1["pol_trials"] >= s1["pol_iters"]
+    assert s2["ms_polish"] > 0 and s2["ms_cd"] > 0
+    assert all(s2[kk] == 0 for kk in ("cd_iters", "pol_iters", "pol_trials", "pol_dogleg", "coll_coarse"))
