@@ -1233,6 +1233,92 @@ __device__ __forceinline__ void line_search_lds(RobotRef rb, int n, const Target
     wave_lds_sync();  // the records are free for the next iteration's writes
 }
 
+// ----------------------------------------------------------------------------
+// Single-coordinate trial (eq. single-coord): only joint `is` moves, from ts
+// to tnew, so the trial pose is the current one turned about that joint's
+// axis zs (the same end-effector pose a full FK gives): with u = P_ee - P_is,
+// z x u = js and Rodrigues' formula, P' = P_ee + sin(d) (z x u) + (1 - cos d)
+// z x (z x u), and q_err' = q_err (x) conj(q_z(d)).  rp0 is the residual
+// position t - P_ee, q0 the error quaternion at theta; returns the cost.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ float single_trial_cost(Quat q0, V3 zs, V3 js, V3 rp0, float ts, float tnew) {
+    const V3 zjs = cross(zs, js);
+    float sh, ch;
+    sincos_cw(0.5f * (tnew - ts), &sh, &ch);
+    const float sd = 2.f * sh * ch, omc = 2.f * sh * sh;
+    const V3 rp = axpy(-omc, zjs, axpy(-sd, js, rp0));
+    const Quat qn = qmul_conj_axis(q0, zs, ch, sh);
+    const float vn = sqrtf(qn.x * qn.x + qn.y * qn.y + qn.z * qn.z);
+    const float ph = 2.f * atan2f(vn, fabsf(qn.w));
+    return 0.5f * (dot(rp, rp) + ph * ph);
+}
+
+// The single-coordinate trials alpha = 1, 1/beta, ..., 1/beta^A spread over
+// the wave like the LDS line search: each lane that reaches them writes its
+// joint's axis and lever, the residual, its joint value, limits and step to
+// the wave's LDS rows (slot = rank among those lanes; 17 + A + 1 <= 26 rows
+// of 64, within the line-search rows of any bucket), tasks (lane, alpha) run
+// ceil(lanes x (A + 1) / 64) passes, and each lane takes its first trial
+// below c0 as the sequential loop does (same values, same choice).
+__device__ __forceinline__ void single_coord_lds(const KParams& kp, Quat q0, V3 zs, V3 js, V3 rp0, float ts,
+                                                 float los, float his, float step, float c0, float& t_out,
+                                                 bool& done, Counters& cnt, float* __restrict__ ws) {
+    const int A1 = kp.ls_A + 1;
+    const uint64_t need = __ballot(!done);
+    if (need == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int nneed = __popcll(need);
+    const int ntask = nneed * A1;
+    const int myrank = __popcll(need & ((1ull << lane) - 1ull));
+    float* __restrict__ wr = ws;              // [17][64] by rank
+    float* __restrict__ wc = ws + 17 * 64;    // [A + 1][64] by rank
+    if (!done) {
+        const float rec[17] = {zs.x, zs.y, zs.z, js.x, js.y, js.z, rp0.x, rp0.y, rp0.z,
+                               q0.w, q0.x, q0.y, q0.z, ts, los, his, step};
+#pragma unroll
+        for (int f = 0; f < 17; ++f) wr[f * 64 + myrank] = rec[f];
+    }
+    wave_lds_sync();
+    // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 576:
+    // the FP32 product with the rounded reciprocal floors exactly
+    const float inv_need = 1.f / (float)nneed;
+    for (int base = 0; base < ntask; base += 64) {
+        const int t = base + lane;
+        if (t < ntask) {
+            const int i = (int)(((float)t + 0.5f) * inv_need);  // trial index 0..A
+            const int r = t - i * nneed;
+            float a = 1.f;
+#pragma unroll
+            for (int k = 1; k <= kLsSpread; ++k)
+                if (k <= i) a *= kp.inv_beta;
+            const V3 z = mk(wr[0 * 64 + r], wr[1 * 64 + r], wr[2 * 64 + r]);
+            const V3 jv = mk(wr[3 * 64 + r], wr[4 * 64 + r], wr[5 * 64 + r]);
+            const V3 r0 = mk(wr[6 * 64 + r], wr[7 * 64 + r], wr[8 * 64 + r]);
+            const Quat q{wr[9 * 64 + r], wr[10 * 64 + r], wr[11 * 64 + r], wr[12 * 64 + r]};
+            const float tsr = wr[13 * 64 + r];
+            const float tnew = clampf(fmaf(a, wr[16 * 64 + r], tsr), wr[14 * 64 + r], wr[15 * 64 + r]);
+            wc[i * 64 + r] = single_trial_cost(q, z, jv, r0, tsr, tnew);
+        }
+    }
+    wave_lds_sync();
+    if (!done) {
+        int first = -1;
+#pragma unroll
+        for (int k = kLsSpread; k >= 0; --k)
+            if (k < A1 && wc[k * 64 + myrank] < c0) first = k;
+        cnt.pol_trials += first >= 0 ? (uint32_t)(first + 1) : (uint32_t)A1;
+        if (first >= 0) {
+            float a = 1.f;
+#pragma unroll
+            for (int k = 1; k <= kLsSpread; ++k)
+                if (k <= first) a *= kp.inv_beta;
+            t_out = clampf(fmaf(a, step, ts), los, his);
+            done = true;
+        }
+    }
+    wave_lds_sync();  // the rows are free for the next writes
+}
+
 // Line-search forms of pj_ik_iter: sequential, spread over the wave through
 // shuffles, spread through the wave's LDS records.
 constexpr int kLsSeq = 0;
@@ -1517,11 +1603,7 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
                 }
                 step = hbest > 0.f ? clampf(gbest / hbest, -R, R) : 0.f;
             }
-            // Only joint `is` moves, so a trial pose is the current one turned
-            // about that joint's axis (the same end-effector pose a full FK
-            // gives): with u = P_ee - P_is, z x u = Jp[is] and Rodrigues'
-            // formula, P' = P_ee + sin(d) (z x u) + (1 - cos d) z x (z x u),
-            // and q_err' = q_err (x) conj(q_z(d)).
+            // trials by rigid rotation about joint `is` (single_trial_cost)
             V3 zs = Z[0], js = Jp[0];
             float ts = th[0], los = rb->lo[0], his = rb->hi[0];
 #pragma unroll
@@ -1534,30 +1616,33 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
                     his = rb->hi[j];
                 }
             }
-            const V3 zjs = cross(zs, js);
             const V3 rp0 = mk(e6[0], e6[1], e6[2]);
-            float alpha2 = 1.f;
-            for (int i = 0; i <= kp.ls_A; ++i) {
-                if (wave_all(done)) break;
-                if (!done) {
-                    const float tnew = clampf(fmaf(alpha2, step, ts), los, his);
-                    float sh, ch;
-                    sincos_cw(0.5f * (tnew - ts), &sh, &ch);
-                    const float sd = 2.f * sh * ch, omc = 2.f * sh * sh;
-                    const V3 rp = axpy(-omc, zjs, axpy(-sd, js, rp0));
-                    const Quat qn = qmul_conj_axis(q0, zs, ch, sh);
-                    const float vn = sqrtf(qn.x * qn.x + qn.y * qn.y + qn.z * qn.z);
-                    const float ph = 2.f * atan2f(vn, fabsf(qn.w));
-                    const float c1 = 0.5f * (dot(rp, rp) + ph * ph);
-                    ++cnt.pol_trials;
-                    if (c1 < c0) {
+            if (LS == kLsLds && kp.ls_A <= kLsSpread) {
+                float tnew = ts;
+                const bool was = done;
+                single_coord_lds(kp, q0, zs, js, rp0, ts, los, his, step, c0, tnew, done, cnt, lsw);
+                if (done && !was) {
 #pragma unroll
-                        for (int j = 0; j < NM; ++j)
-                            if (j < n && j == is) th[j] = tnew;
-                        done = true;
-                    }
+                    for (int j = 0; j < NM; ++j)
+                        if (j < n && j == is) th[j] = tnew;
                 }
-                alpha2 *= kp.inv_beta;
+            } else {
+                float alpha2 = 1.f;
+                for (int i = 0; i <= kp.ls_A; ++i) {
+                    if (wave_all(done)) break;
+                    if (!done) {
+                        const float tnew = clampf(fmaf(alpha2, step, ts), los, his);
+                        const float c1 = single_trial_cost(q0, zs, js, rp0, ts, tnew);
+                        ++cnt.pol_trials;
+                        if (c1 < c0) {
+#pragma unroll
+                            for (int j = 0; j < NM; ++j)
+                                if (j < n && j == is) th[j] = tnew;
+                            done = true;
+                        }
+                    }
+                    alpha2 *= kp.inv_beta;
+                }
             }
         }
         // --- random perturbation when every step failed
