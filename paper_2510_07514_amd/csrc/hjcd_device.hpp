@@ -354,6 +354,80 @@ __device__ __forceinline__ void perturb(RB rb, int n, float* th,
     }
 }
 
+// Order this wave's LDS accesses (in-order execution within a wave; this
+// keeps the compiler from moving loads and stores across it).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// LDS floats per wave of perturb_spread.
+template <int NM>
+__host__ __device__ constexpr int perturb_wave_floats() {
+    return (NM + 3) * 64;
+}
+
+// The same perturbation for the lanes with `want`, its draws spread over the
+// wave: each such lane writes its seed index, target key and iteration to
+// slot r (its rank) of the wave's LDS rows; task t = q nneed + r draws the
+// Box-Muller pair q (joints 2q, 2q + 1: block q / 2, words 2 (q % 2) and
+// 2 (q % 2) + 1) of slot r and stores the normals at [2q][r], [2q + 1][r];
+// each lane then applies its n normals as perturb does.  The draws and
+// updates are perturb's, so the results are the same; the wave runs
+// ceil(lanes x ceil(n / 2) / 64) passes of one pair each instead of every
+// pair of the lanes that perturb.  Called by the whole wave (uniform control
+// flow); `ws` holds perturb_wave_floats<NM>() floats of this wave's LDS.
+template <int NM, typename RB>
+__device__ __forceinline__ void perturb_spread(RB rb, int n, float* th, bool want, uint64_t seed, uint32_t m,
+                                               uint32_t tkey, uint32_t stage, uint32_t iter, float mu, float sigma,
+                                               float* __restrict__ ws) {
+    const uint64_t need = __ballot(want);
+    if (need == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63u);
+    const int nneed = __popcll(need);
+    const int npair = (n + 1) >> 1;
+    const int ntask = nneed * npair;
+    const int myrank = __popcll(need & ((1ull << lane) - 1ull));
+    float* __restrict__ wz = ws;                           // [NM][64] normals by rank
+    uint32_t* __restrict__ wk = (uint32_t*)(ws + NM * 64);  // [3][64] m, tkey, iter by rank
+    if (want) {
+        wk[0 * 64 + myrank] = m;
+        wk[1 * 64 + myrank] = tkey;
+        wk[2 * 64 + myrank] = iter;
+    }
+    wave_lds_sync();
+    // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 1024:
+    // the FP32 product with the rounded reciprocal floors exactly
+    const float inv_need = 1.f / (float)nneed;
+    for (int base = 0; base < ntask; base += 64) {
+        const int t = base + lane;
+        if (t < ntask) {
+            const int q = (int)(((float)t + 0.5f) * inv_need);  // pair index
+            const int r = t - q * nneed;
+            const U4 x = draw(seed, wk[0 * 64 + r], wk[1 * 64 + r], stage, wk[2 * 64 + r], (uint32_t)(q >> 1));
+            const bool hi = (q & 1) != 0;
+            const uint32_t w0 = hi ? x.c : x.a, w1 = hi ? x.d : x.b;
+            const float rad = sqrtf(-2.f * logf(uni24(w0)));
+            float sn, cs;
+            sincospif(2.f * uni24(w1), &sn, &cs);
+            wz[(2 * q) * 64 + r] = rad * cs;
+            if (2 * q + 1 < n) wz[(2 * q + 1) * 64 + r] = rad * sn;
+        }
+    }
+    wave_lds_sync();
+    if (want) {
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            if (j < n) {
+                const float z = wz[j * 64 + myrank];
+                th[j] = clampf(th[j] + mu + sigma * z, rb->lo[j], rb->hi[j]);
+            }
+        }
+    }
+    wave_lds_sync();  // the rows are free for the next writes
+}
+
 template <int NM>
 __device__ __forceinline__ void uniform_seed(const DevRobot* __restrict__ rb, int n, float* th,
                                              uint64_t seed, uint32_t m, uint32_t tkey) {
@@ -509,16 +583,19 @@ __device__ __forceinline__ void cd_candidate(V3 P, V3 z, float tj, float lo, flo
 // fresh seed starts with frozen = !live).  out_err is the residual at the
 // configuration the last iteration produced.
 // ----------------------------------------------------------------------------
-template <int NM>
+// PSPREAD: the perturbations of rejected moves run through perturb_spread
+// on the wave's LDS rows `pws` (same results).
+template <int NM, bool PSPREAD = false>
 __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, const Target& tg, const KParams& kp,
                                        uint32_t m, uint32_t tkey, float* th, bool live, bool& frozen,
                                        Counters& cnt, float* __restrict__ traj, int64_t S, int64_t s, int k0,
-                                       int k1, Err& out_err) {
+                                       int k1, Err& out_err, float* __restrict__ pws = nullptr) {
     float last_ep = 0.f, last_phi = 0.f;
     V3 P[NM], Z[NM];
     float delta = kp.delta0 * powf(kp.delta_decay, (float)k0);
     for (int k = k0; k < k1; ++k) {
         if (wave_all(frozen) && !traj) break;
+        bool pert = false;  // this iteration's move was rejected
         if (!frozen) {
             Frame ee;
             fk_chain<NM, true>(rb, n, th, P, Z, ee);
@@ -638,13 +715,18 @@ __device__ __forceinline__ void po_ccd(const DevRobot* __restrict__ rb, int n, c
                         if (j == jb) th[j] += db;
                     }
                 } else {
-                    perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_CD, (uint32_t)k, kp.mu, kp.sigma);
+                    pert = true;
                     ++cnt.cd_perturb;
                 }
             }
         } else if (live) {
             write_traj<NM>(traj, n, S, s, k, th, last_ep, last_phi);
         }
+        // rejected: random perturbation
+        if (PSPREAD)
+            perturb_spread<NM>(rb, n, th, pert, kp.seed, m, tkey, STAGE_CD, (uint32_t)k, kp.mu, kp.sigma, pws);
+        else if (pert)
+            perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_CD, (uint32_t)k, kp.mu, kp.sigma);
         delta *= kp.delta_decay;
     }
     Frame ee;
@@ -1134,14 +1216,6 @@ __device__ __forceinline__ void line_search_spread(RobotRef rb, int n, const Tar
 template <int NM>
 __host__ __device__ constexpr int ls_wave_floats() {
     return (2 * NM + 7 + kLsSpread) * 64;
-}
-
-// Order this wave's LDS accesses (in-order execution within a wave; this
-// keeps the compiler from moving loads and stores across it).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int NM>
@@ -1646,10 +1720,12 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
             }
         }
         // --- random perturbation when every step failed
-        if (!done) {
+        if (LS == kLsLds) {
+            perturb_spread<NM>(rb, n, th, !done, kp.seed, m, tkey, STAGE_POLISH, (uint32_t)it, kp.mu, kp.sigma, lsw);
+        } else if (!done) {
             perturb<NM>(rb, n, th, kp.seed, m, tkey, STAGE_POLISH, (uint32_t)it, kp.mu, kp.sigma);
-            ++cnt.pol_perturb;
         }
+        if (!done) ++cnt.pol_perturb;
     }
 }
 

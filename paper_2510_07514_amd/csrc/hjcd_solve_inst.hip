@@ -55,6 +55,24 @@ __device__ __forceinline__ float* ls_records() {
     }
 }
 
+// PO-CCD's perturbation rows of this wave in the workgroup's dynamic LDS.
+template <int NM>
+__device__ __forceinline__ float* cd_records() {
+    extern __shared__ float ls_dyn[];
+    return ls_dyn + (threadIdx.x >> 6) * perturb_wave_floats<NM>();
+}
+
+// PO-CCD perturbations spread through LDS (same results) in the buckets
+// where it measured faster: 7 joints (k_cd 1.38 -> 1.32 ms on 1,000 x 1,024)
+// and 24 (4.45 -> 4.29 ms on 2,000 x 256); at 12, 20 and 32 joints it was
+// 2-5% slower (there more lanes perturb per wave and the passes add up).
+constexpr bool kCdPerturbSpread = HJCD_NM <= 8 || HJCD_NM == 24;
+
+template <int NM>
+constexpr size_t cd_lds_bytes(int threads) {
+    return kCdPerturbSpread ? (size_t)(threads / 64) * perturb_wave_floats<NM>() * sizeof(float) : 0;
+}
+
 // ----------------------------------------------------------------------------
 // Per-seed solve: seed init, PO-CCD and/or PJ-IK, results to HBM.
 // ----------------------------------------------------------------------------
@@ -110,8 +128,8 @@ __device__ __forceinline__ void solve_body(const SolveArgs& a, bool do_cd, bool 
     Err e{};
     if (do_cd) {
         bool frozen = !live;
-        po_ccd<NM>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s, 0, a.kp.cd_sweeps,
-                   e);
+        po_ccd<NM, kCdPerturbSpread>(a.rb, n, tg, a.kp, sl.m, sl.tkey, th, live, frozen, cnt, a.traj, a.S, sl.s,
+                                     0, a.kp.cd_sweeps, e, kCdPerturbSpread ? cd_records<NM>() : nullptr);
     }
     if (do_polish) {
         bool frozen = !live;
@@ -380,7 +398,7 @@ static hipError_t launch_solve_stats(const SolveArgs& a, hipStream_t st) {
             hipLaunchKernelGGL((k_cd_pair<HJCD_NM, STATS>), dim3(nb2), dim3(bt), 0, st, a);
         }
     } else if (a.do_cd)
-        hipLaunchKernelGGL((k_cd<HJCD_NM, STATS>), dim3(nb), dim3(bt), 0, st, a);
+        hipLaunchKernelGGL((k_cd<HJCD_NM, STATS>), dim3(nb), dim3(bt), cd_lds_bytes<HJCD_NM>(bt), st, a);
     else if (!a.do_polish)
         hipLaunchKernelGGL((k_seed<HJCD_NM>), dim3(nb), dim3(bt), 0, st, a);
     else if (sf > 1 && a.variant == 1)
