@@ -364,6 +364,17 @@ def test_polish_trajectory_far(H, ctx, name):
     _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=12, params=W.default_params(), min_rows=0.70)
 
 
+@pytest.mark.parametrize("ls_A,min_rows", [(0, 0.85), (1, 0.85), (9, 0.82)])
+def test_polish_line_search_lengths(H, ctx, ls_A, min_rows):
+    """PJ-IK with A = 0 and 1 (the spread line search, single-coordinate and
+    perturbation passes at their smallest) and A = 9 (beyond the spread
+    forms: the sequential loops of the same bucket) against the oracle.  Rows
+    compared on the CPU (oracle margins and shadows): 0.885, 0.882, 0.849."""
+    say(f"case: polish trajectory far panda, ls_A = {ls_A}")
+    rob = _robots()["panda"]
+    _check_stage(H, ctx, rob, "polish", T=6, M=48, seed=13, params=W.default_params(ls_A=ls_A), min_rows=min_rows)
+
+
 LONG_CHAINS = {
     # name: (parameters, min rows compared CD, near, far)
     "random20": (dict(cd_sweeps=40, polish_iters=40), 0.76, 0.90, 0.78),
