@@ -328,16 +328,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SolveOcc<NM
     }
     Counters cnt;
     Err er{};
+    // the wave's LDS rows of the spread line search, single-coordinate trials
+    // and perturbations (both stages), in the buckets that use them
+    constexpr int LS = SolveOcc<NM, 0>::ls;
+    static_assert(!kCdPerturbSpread || LS == kLsLds, "PO-CCD's perturbation rows live in the line-search rows");
+    static_assert(perturb_wave_floats<NM>() <= ls_wave_floats<NM>(), "rows too small");
+    __shared__ float rows[LS == kLsLds ? 4 * ls_wave_floats<NM>() : 1];
+    float* const wrows = LS == kLsLds ? rows + (threadIdx.x >> 6) * ls_wave_floats<NM>() : nullptr;
     if (blk.stage == SERVE_CD) {
         bool frozen = !live || (st & SLOT_CD_FROZEN);
-        po_ccd<NM>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er);
+        po_ccd<NM, kCdPerturbSpread>(a.rb, n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1,
+                                     er, wrows);
         if (frozen) st |= SLOT_CD_FROZEN;
     } else {
         bool frozen = !live || (st & SLOT_POL_FROZEN);
-        constexpr int LS = SolveOcc<NM, 0>::ls;
-        __shared__ float ls_rec[LS == kLsLds ? 4 * ls_wave_floats<NM>() : 1];
         pj_ik<NM, LS>(robot_ref(a.rb), n, tg, a.kp, m, tkey, th, live, frozen, cnt, nullptr, 0, s, blk.k0, blk.k1, er,
-                      true, LS == kLsLds ? ls_rec + (threadIdx.x >> 6) * ls_wave_floats<NM>() : nullptr);
+                      true, wrows);
         // the exit test of iteration k1 (or the one after the last iteration)
         // on the state this chunk leaves: a seed converged by the chunk's last
         // step is eligible for the collision check at this chunk's end
