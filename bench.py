@@ -518,7 +518,8 @@ def main():
     ap.add_argument("--serve-prefix", type=int, default=10000,
                     help="first requests of each stream run by both modes (the same-request comparison)")
     ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
-    ap.add_argument("--serve-chunk", type=int, default=4, help="iterations per serving chunk")
+    ap.add_argument("--serve-chunk", type=int, default=20,
+                    help="iterations per serving chunk (20 = a whole stage at the default iterations)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()

@@ -353,7 +353,8 @@ void hjcd_plan_destroy(hjcd_plan plan);
  * seeds fit in the resident slot pool (sized from a device-memory budget),
  * keeps every admitted seed's state resident in device memory, and advances
  * all of them together in chunks of `chunk_iters` iterations (continuous
- * batching: requests join and leave between chunks).  A target retires at the
+ * batching: requests join and leave between chunks; a request whose PO-CCD
+ * ends in a chunk also runs its first PJ-IK chunk in the same step).  A target retires at the
  * end of the first chunk in which one of its PJ-IK-converged seeds is
  * collision free within succ_pos / succ_ori (its best such seed by (cost,
  * index)); otherwise it returns its best seed by (collision, cost, index)
@@ -378,7 +379,9 @@ typedef struct {
                               64-slot blocks; HJCD_E_NOMEM below one block (0 = a quarter of
                               free memory, at most 8 GiB) */
     int32_t max_targets;   /* resident targets (0 = slots / 32, between 64 and 2^20) */
-    int32_t chunk_iters;   /* iterations per chunk (>= 1) */
+    int32_t chunk_iters;   /* iterations per chunk (>= 1); at least the stage lengths (one chunk per
+                              stage, the first PJ-IK chunk in the step that ends PO-CCD) gives the
+                              lowest latency, shorter chunks retire targets at more points */
     int32_t max_queue;     /* pending requests accepted before submit returns HJCD_E_BUSY */
 } hjcd_server_config;
 

@@ -168,7 +168,7 @@ hjcd_status server_alloc_batched(hjcd_server s) {
     s->st.tgt_key = s->d_tkey;
     s->st.Tc = Tc;
     s->up_cap = align16(sizeof(ServeAdmit) * Tc) + align16(sizeof(float) * 7 * Tc) +
-                2 * align16(sizeof(ServeBlock) * nb_max) + align16(sizeof(int32_t) * nb_max) +
+                3 * align16(sizeof(ServeBlock) * nb_max) + align16(sizeof(int32_t) * nb_max) +
                 3 * align16(sizeof(int32_t) * Tc) + align16(sizeof(int64_t) * Tc);
     s->down_cap = align16(sizeof(int32_t) * Tc) + align16(sizeof(float) * Tc * (s->n + 3));
     s->d_up = dev_alloc<char>(s->up_cap, ok);
@@ -272,24 +272,35 @@ hjcd_status batched_step(hjcd_server s) {
     }
     if (s->active.empty()) return HJCD_OK;
 
-    // 2. the chunk's lists: every resident block; the PJ-IK blocks again for
-    //    the collision check (every lane at the stage's end); PJ-IK targets
-    //    still running for the decision
-    int32_t nb = 0, nchk = 0, nt = 0;
+    // 2. the chunk's lists: every resident block at its stage's next
+    //    iterations; the blocks whose PO-CCD ends in this chunk again, for
+    //    their first PJ-IK chunk in a second launch of the same step; the
+    //    PJ-IK blocks for the collision check (every lane at the stage's end);
+    //    PJ-IK targets still running for the decision.  A request's PJ-IK
+    //    chunks span the same request-local iterations either way, so running
+    //    its first one in the step that ends its PO-CCD leaves every decision
+    //    unchanged and saves a round trip.
+    const auto cd_ends = [&](const Request* r) {
+        return r->stage == SERVE_CD && std::min(r->iter + c, p.cd_sweeps) >= p.cd_sweeps;
+    };
+    int32_t nb = 0, nb2 = 0, nchk = 0, nt = 0;
     int64_t resident = 0;
     for (auto& up : s->active) {
         resident += (int64_t)up->nblocks * 64;
         nb += up->nblocks;
-        if (up->stage == SERVE_POLISH) {
+        const bool fuse = cd_ends(up.get());
+        if (fuse) nb2 += up->nblocks;
+        if (up->stage == SERVE_POLISH || fuse) {
             nchk += up->nblocks;
             for (int k = 0; k < up->n_targets; ++k) nt += up->status[k] == 0;
         }
     }
     (void)nb_max;
-    ServeBlock *d_blk, *d_chk;
+    ServeBlock *d_blk, *d_blk2, *d_chk;
     int32_t *d_all, *d_rt, *d_rn, *d_rfinal;
     int64_t* d_rfirst;
     ServeBlock* h_blk = ar.take<ServeBlock>(nb, &d_blk);
+    ServeBlock* h_blk2 = ar.take<ServeBlock>(nb2, &d_blk2);
     ServeBlock* h_chk = ar.take<ServeBlock>(nchk, &d_chk);
     int32_t* h_all = ar.take<int32_t>(nchk, &d_all);
     int32_t* h_rt = ar.take<int32_t>(nt, &d_rt);
@@ -297,18 +308,23 @@ hjcd_status batched_step(hjcd_server s) {
     int32_t* h_rn = ar.take<int32_t>(nt, &d_rn);
     int32_t* h_rfinal = ar.take<int32_t>(nt, &d_rfinal);
     if (ar.off > s->up_cap) return fail(HJCD_E_INTERNAL, "serving upload arena overflow");
-    int32_t ib = 0, ic = 0, it = 0;
+    int32_t ib = 0, ib2 = 0, ic = 0, it = 0;
     for (auto& up : s->active) {
         Request* r = up.get();
-        const bool pol = r->stage == SERVE_POLISH;
-        const int len = pol ? p.polish_iters : p.cd_sweeps;
+        const bool cd = r->stage == SERVE_CD;
+        const bool fuse = cd_ends(r);
+        const int len = cd ? p.cd_sweeps : p.polish_iters;
         const int k0 = r->iter, k1 = std::min(r->iter + c, len);
-        const bool last = pol && k1 >= len;
+        // this step's PJ-IK iterations: the stage's next chunk, or its first
+        const int q0 = cd ? 0 : k0, q1 = cd ? std::min(c, p.polish_iters) : k1;
+        const bool pol = !cd || fuse;
+        const bool last = pol && q1 >= p.polish_iters;
         for (int b = 0; b < r->nblocks; ++b) {
-            const ServeBlock blk{(int32_t)(r->base / 64) + b, r->stage, k0, k1};
-            h_blk[ib++] = blk;
+            const int32_t blk_id = (int32_t)(r->base / 64) + b;
+            h_blk[ib++] = ServeBlock{blk_id, r->stage, k0, k1};
+            if (fuse) h_blk2[ib2++] = ServeBlock{blk_id, SERVE_POLISH, q0, q1};
             if (pol) {
-                h_chk[ic] = blk;
+                h_chk[ic] = ServeBlock{blk_id, SERVE_POLISH, q0, q1};
                 h_all[ic++] = last ? 1 : 0;
             }
         }
@@ -333,6 +349,12 @@ hjcd_status batched_step(hjcd_server s) {
     ca.nb = nb;
     ca.kp = kparams(p);
     HIP_TRY(launch_serve_chunk(ca, s->stream));
+    if (nb2 > 0) {  // first PJ-IK chunk of the requests whose PO-CCD just ended
+        ServeChunkArgs c2 = ca;
+        c2.blocks = d_blk2;
+        c2.nb = nb2;
+        HIP_TRY(launch_serve_chunk(c2, s->stream));
+    }
     if (nchk > 0) {
         ServeCheckArgs ck{};
         ck.rb = s->robot->dev;
@@ -377,7 +399,8 @@ hjcd_status batched_step(hjcd_server s) {
     std::vector<std::unique_ptr<Request>> done;
     for (auto& up : s->active) {
         Request* r = up.get();
-        if (r->stage == SERVE_POLISH) {
+        const bool fuse = cd_ends(r);
+        if (r->stage == SERVE_POLISH || fuse) {
             for (int k = 0; k < r->n_targets; ++k) {
                 if (r->status[k] != 0) continue;
                 const int32_t stt = h_status[it];
@@ -390,11 +413,12 @@ hjcd_status batched_step(hjcd_server s) {
                 it++;
             }
         }
-        const int len = r->stage == SERVE_CD ? p.cd_sweeps : p.polish_iters;
-        r->iter = std::min(r->iter + c, len);
-        if (r->iter >= len && r->stage == SERVE_CD) {
+        if (fuse) {
             r->stage = SERVE_POLISH;
-            r->iter = 0;
+            r->iter = std::min(c, p.polish_iters);
+        } else {
+            const int len = r->stage == SERVE_CD ? p.cd_sweeps : p.polish_iters;
+            r->iter = std::min(r->iter + c, len);
         }
         if (r->n_done == r->n_targets) {
             r->done = t_done;

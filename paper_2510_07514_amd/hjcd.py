@@ -534,7 +534,7 @@ class Server:
 
 
 def hjcd_server_create(ctx, robot, scene, params, mode=HJCD_SERVE_BATCHED, max_slots=0, hbm_budget=0,
-                       max_targets=0, chunk_iters=4, max_queue=0) -> Server:
+                       max_targets=0, chunk_iters=20, max_queue=0) -> Server:
     cfg = hjcd_server_config(mode, max_slots, hbm_budget, max_targets, chunk_iters, max_queue)
     h = _vp()
     _check(_lib.hjcd_server_create(ctx.handle, robot.handle, scene.handle if scene else None, C.byref(params),
