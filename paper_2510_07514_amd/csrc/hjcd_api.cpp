@@ -824,6 +824,7 @@ hjcd_status hjcd_collide(hjcd_ctx c, hjcd_robot r, hjcd_scene sc, int64_t S, con
     a.grid = scene_grid(sc, r);
     a.flag = flag;
     a.counters = nullptr;
+    a.n_pairs = r->host.n_pairs;
     HIP_TRY(launch_collide(a, (hipStream_t)stream));
     return HJCD_OK;
 }
@@ -1200,6 +1201,7 @@ static hjcd_status solve_impl(hjcd_ctx c, int32_t n_robots, const hjcd_robot* ro
         a.grid = scene_grid(sc, robots[ri]);
         a.flag = (uint8_t*)w_flag + base;
         a.counters = ss.counters();
+        a.n_pairs = robots[ri]->host.n_pairs;
         HIP_TRY(launch_collide(a, st));
     }
     if ((s = ss.mark(SS_COLLIDE)) != HJCD_OK) return s;

@@ -208,7 +208,13 @@ __device__ __forceinline__ void grid_obstacles(const DevRobot* __restrict__ rb, 
 
 // Collision test of one lane whose joint values are q[i * q_stride + s];
 // inactive lanes count as done so the wave can leave early.  Returns the
-// collision flag of an active lane.
+// collision flag of an active lane.  ENV: the obstacle tests, link by link;
+// SELF: every link frame to the wave's LDS rows and the self pairs after the
+// walk.  A lane's tests, counts and early exits are those of the one-pass
+// form whichever parts a call runs (a lane that collides stops testing; a
+// wave leaves once all its lanes collide), so running ENV, then SELF on the
+// lanes still free, gives the same flags and counters.
+template <bool ENV = true, bool SELF = true>
 __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, int n, float* lds, int lane,
                                              bool active, const float* __restrict__ q, int64_t q_stride,
                                              int64_t s, const float* __restrict__ os, int n_osph,
@@ -216,7 +222,7 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
                                              uint32_t& n_coarse, uint32_t& n_fine) {
     bool hit = !active;
     // environment, link by link along the chain walk (the frame is in
-    // registers); every frame is kept in LDS for the self pairs
+    // registers); for the self pairs every frame is kept in LDS
     Frame F = identity_frame();
     for (int l = 0; l <= n; ++l) {
         if (l > 0) {
@@ -224,7 +230,8 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
             chain_step(rb, l - 1, th, F);
         }
         if (wave_all(hit)) break;  // the self pairs are skipped too
-        lds_store_frame(lds, l, lane, F);
+        if (SELF) lds_store_frame(lds, l, lane, F);
+        if (!ENV) continue;
         const float Rc = rb->coarse[l][3];
         if (Rc < 0.f) continue;
         const V3 cc = xform(F, rb->coarse[l][0], rb->coarse[l][1], rb->coarse[l][2]);
@@ -285,6 +292,7 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
             box_obstacle(rb, F, f0, fc, ob + 8 * o, !hit && box_d2(cc, ob + 8 * o) < Rc * Rc, hit, n_coarse, n_fine);
     }
     // self collision on the allowed link pairs
+    if (!SELF) return hit;
     for (int pi = 0; pi < rb->n_pairs && !wave_all(hit); ++pi) {
         const int la = rb->pair_a[pi], lb = rb->pair_b[pi];
         const Frame Fa = lds_load_frame(lds, la, lane);
@@ -317,19 +325,70 @@ __device__ __forceinline__ bool collide_lane(const DevRobot* __restrict__ rb, in
     return hit;
 }
 
-__global__ __launch_bounds__(64) void k_collide(CollideArgs a) {
-    extern __shared__ float lds[];
-    const int lane = threadIdx.x;
-    const int64_t s = (int64_t)blockIdx.x * 64 + lane;
+// Obstacle tests, one seed per lane: no LDS, so the occupancy is set by
+// registers alone (the link frames of the self pairs, 7 floats per link and
+// lane in LDS, would hold it to a few waves per CU on long chains).
+__global__ __launch_bounds__(256) void k_collide_env(CollideArgs a) {
+    const int lane = (int)(threadIdx.x & 63u);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = s < a.S;
     uint32_t n_coarse = 0, n_fine = 0;
-    const bool hit = collide_lane(a.rb, a.n, lds, lane, live, a.q, a.q_stride, s, a.osph, a.n_osph, a.obox,
-                                  a.n_obox, a.grid, n_coarse, n_fine);
+    const bool hit = collide_lane<true, false>(a.rb, a.n, nullptr, lane, live, a.q, a.q_stride, s, a.osph,
+                                               a.n_osph, a.obox, a.n_obox, a.grid, n_coarse, n_fine);
     if (live) a.flag[s] = hit ? 1 : 0;
     if (a.counters) {
         Counters c;
         c.coll_coarse = live ? n_coarse : 0u;
         c.coll_fine = live ? n_fine : 0u;
+        flush_counters(c, a.counters, true);
+    }
+}
+
+// Self pairs of the seeds the obstacle tests left free.  Wave w scans seeds
+// [w P, (w + 1) P) 64 at a time and queues the free ones in LDS; each time
+// 64 are queued it tests them, one per lane (frames to LDS, then the pairs),
+// and the rest at the end, so the LDS-bound pass runs on full waves of the
+// seeds that need it (on cluttered scenes a few percent).
+constexpr int kSelfQueue = 128;
+
+__global__ __launch_bounds__(64) void k_collide_self(CollideArgs a, int64_t P) {
+    extern __shared__ float lds[];
+    const int lane = (int)threadIdx.x;
+    int32_t* queue = (int32_t*)(lds + (a.n + 1) * kFrameFloats * 64);  // [kSelfQueue], wave-local
+    const int64_t b0 = (int64_t)blockIdx.x * P;
+    const int64_t b1 = b0 + P < a.S ? b0 + P : a.S;
+    uint32_t n_coarse = 0, n_fine = 0;
+    int qn = 0;  // queued seeds (uniform)
+    auto run = [&](int count) {
+        const bool act = lane < count;
+        const int64_t s = b0 + (act ? (int64_t)queue[lane] : 0);  // queued as offsets from b0
+        const bool hit = collide_lane<false, true>(a.rb, a.n, lds, lane, act, a.q, a.q_stride, s, a.osph, a.n_osph,
+                                                   a.obox, a.n_obox, a.grid, n_coarse, n_fine);
+        if (act && hit) a.flag[s] = 1;
+    };
+    for (int64_t base = b0; base < b1; base += 64) {
+        const int64_t s = base + lane;
+        const bool free = s < b1 && a.flag[s] == 0;
+        const uint64_t m = __ballot(free);
+        if (free) queue[qn + __popcll(m & ((1ull << lane) - 1ull))] = (int32_t)(s - b0);
+        qn += __popcll(m);  // qn < 64 before, so at most 127 entries
+        wave_lds_sync();
+        if (qn >= 64) {
+            run(64);
+            wave_lds_sync();
+            const int rest = qn - 64;
+            const int32_t t = lane < rest ? queue[64 + lane] : 0;
+            wave_lds_sync();
+            if (lane < rest) queue[lane] = t;
+            qn = rest;
+            wave_lds_sync();
+        }
+    }
+    if (qn > 0) run(qn);
+    if (a.counters) {
+        Counters c;
+        c.coll_coarse = n_coarse;
+        c.coll_fine = n_fine;
         flush_counters(c, a.counters, true);
     }
 }
@@ -687,8 +746,17 @@ hipError_t launch_fk(const DevRobot* rb, int n, int64_t S, const float* q, float
 
 hipError_t launch_collide(const CollideArgs& a, hipStream_t st) {
     if (a.S <= 0) return hipSuccess;
-    const size_t lds = (size_t)(a.n + 1) * kFrameFloats * 64 * sizeof(float);
-    hipLaunchKernelGGL(k_collide, dim3(blocks_for(a.S, 64)), dim3(64), lds, st, a);
+    hipLaunchKernelGGL(k_collide_env, dim3(blocks_for(a.S, 256)), dim3(256), 0, st, a);
+    if (a.n_pairs <= 0) return hipGetLastError();
+    // scanning waves: four rounds of what the LDS lets a 256-CU part hold at
+    // once (160 KB per CU), each scanning a 64-seed multiple
+    const size_t lds = (size_t)(a.n + 1) * kFrameFloats * 64 * sizeof(float) + kSelfQueue * sizeof(int32_t);
+    const int64_t per_cu = (int64_t)((160u << 10) / lds) < 1 ? 1 : (int64_t)((160u << 10) / lds);
+    const int64_t cap = 256 * per_cu * 4;
+    const int64_t waves = (a.S + 63) / 64 < cap ? (a.S + 63) / 64 : cap;
+    const int64_t P = ((a.S + waves - 1) / waves + 63) / 64 * 64;
+    const unsigned nb = (unsigned)((a.S + P - 1) / P);
+    hipLaunchKernelGGL(k_collide_self, dim3(nb), dim3(64), lds, st, a, P);
     return hipGetLastError();
 }
 

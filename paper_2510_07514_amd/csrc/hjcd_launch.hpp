@@ -103,6 +103,7 @@ struct CollideArgs {
     uint8_t* flag;
     unsigned long long* counters;
     ObstacleGrid grid;
+    int32_t n_pairs;  // the robot's self-collision link pairs (0: no self pass)
 };
 
 hipError_t launch_collide(const CollideArgs& a, hipStream_t st);

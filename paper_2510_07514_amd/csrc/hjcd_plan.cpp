@@ -156,6 +156,7 @@ CollideArgs collide_args(hjcd_plan p, int ri) {
     a.grid = scene_grid(p->scene, p->robots[ri]);
     a.flag = p->fl + base;
     a.counters = nullptr;
+    a.n_pairs = p->robots[ri]->host.n_pairs;
     return a;
 }
 
