@@ -398,8 +398,8 @@ __device__ __forceinline__ void perturb_spread(RB rb, int n, float* th, bool wan
     }
     wave_lds_sync();
     // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 1024:
-    // the FP32 product with the rounded reciprocal floors exactly
-    const float inv_need = 1.f / (float)nneed;
+    // its FP32 product with the hardware reciprocal (within 1 ulp) floors exactly
+    const float inv_need = __builtin_amdgcn_rcpf((float)nneed);
     for (int base = 0; base < ntask; base += 64) {
         const int t = base + lane;
         if (t < ntask) {
@@ -1265,9 +1265,9 @@ __device__ __forceinline__ void line_search_lds(RobotRef rb, int n, const Target
         wtg[6 * 64 + myrank] = tg.q.z;
     }
     wave_lds_sync();
-    // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 512,
-    // so its FP32 product with the rounded reciprocal floors exactly
-    const float inv_need = 1.f / (float)nneed;
+    // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 512:
+    // its FP32 product with the hardware reciprocal (within 1 ulp) floors exactly
+    const float inv_need = __builtin_amdgcn_rcpf((float)nneed);
     for (int base = 0; base < ntask; base += 64) {
         const int t = base + lane;
         if (t < ntask) {
@@ -1354,8 +1354,8 @@ __device__ __forceinline__ void single_coord_lds(const KParams& kp, Quat q0, V3 
     }
     wave_lds_sync();
     // (t + 1/2) / nneed is at least 1 / 128 away from an integer and t < 576:
-    // the FP32 product with the rounded reciprocal floors exactly
-    const float inv_need = 1.f / (float)nneed;
+    // its FP32 product with the hardware reciprocal (within 1 ulp) floors exactly
+    const float inv_need = __builtin_amdgcn_rcpf((float)nneed);
     for (int base = 0; base < ntask; base += 64) {
         const int t = base + lane;
         if (t < ntask) {

@@ -153,6 +153,42 @@ def test_collision_flags(H, ctx, which):
     assert checked > 100
 
 
+def test_collision_self_queue_large_launch(H, ctx):
+    """The self-pair pass queues the seeds the obstacle pass left free and tests
+    them 64 at a time; at 1,500,001 seeds each scanning wave covers several
+    64-seed chunks, so queues fill, run and carry their remainder over.  Flags
+    equal those of small launches (one chunk per wave) bit for bit, and the
+    oracle's on a sample."""
+    import torch
+    say("case: collision, self-pair queue at 1,500,001 seeds")
+    b = W.config_batched(T=1, M=1)
+    rob = b.robots[0]
+    rb = H.hjcd_load_robot(ctx, rob)
+    sc = H.hjcd_load_scene(ctx, b.scene.spheres, b.scene.boxes)
+    S = 1_500_001
+    q = W.uniform_configs(np.random.default_rng(9), rob, S)
+    qd = soa(q, rob.dof)
+    flag = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    H.hjcd_collide(ctx, rb, sc, qd, flag)
+    small = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    for a in range(0, S, 4096):
+        e = min(a + 4096, S)
+        H.hjcd_collide(ctx, rb, sc, qd[:, a:e].contiguous(), small[a:e])
+    _sync()
+    fl, fs = flag.cpu().numpy(), small.cpu().numpy()
+    say(f"  colliding {fl.mean():.3f}")
+    assert np.array_equal(fl, fs)
+    rh, sh = O.RobotHandle(rob), O.SceneHandle(b.scene)
+    checked = 0
+    for s_ in np.random.default_rng(10).choice(S, 1500, replace=False):
+        f, md = O.collide(rh, sh, q[s_].astype(np.float64))
+        if abs(md) < 1e-5:
+            continue
+        checked += 1
+        assert fl[s_] == f, (int(s_), md)
+    assert checked > 1000
+
+
 def test_collision_grid_dense_scene(H, ctx):
     """A cluttered scene (100 spheres and 100 boxes of 1-3 cm around the
     Panda-like arm's workspace: the library lists obstacles per grid cell for
