@@ -205,7 +205,7 @@ def empty_scene() -> Scene:
 # ----------------------------------------------------------------------------
 
 def default_params(**over) -> dict:
-    """Parameters of PO-CCD (Alg. 3), PJ-IK (Alg. 4) and the driver (Alg. 2).
+    """Parameters of PO-CCD (Alg. PO-CCD), PJ-IK (Alg. PJ-IK) and the outer loop (Alg. HJCD-IK).
     The paper prints none of these values except that lambda > 0."""
     p = dict(
         cd_sweeps=20, polish_iters=20,
