@@ -29,14 +29,14 @@ template <int NM, int V>
 struct SolveOcc {
     static constexpr int waves = NM <= 8 ? (V == 0 ? 3 : 2) : NM <= 16 ? (V == 0 ? 2 : 1) : (V == 0 ? 1 : 2);
     // line-search form (same results): the shuffle form needs ~50 more live
-    // registers, which would spill at three waves per SIMD, so up to 8 joints
-    // the searching lanes' records go through LDS; so too at 20 and 24 joints,
-    // where it cuts PJ-IK's spills at two waves (24: 188 -> 99 registers;
-    // 24-joint chain, 2,000 x 256: 5.11 -> 3.81 ms; 20-joint streaming launch,
-    // 20,000 x 256: 69.1 -> 64.8 ms).  At 32 joints (one wave, no spills) the
-    // shuffles measured faster (3.93 vs 4.09 ms), at 12 joints the two are
-    // within 1-2%.
-    static constexpr int ls = (NM <= 8 || NM == 20 || NM == 24) ? kLsLds : kLsShfl;
+    // registers, which spill at three waves per SIMD up to 8 joints and at two
+    // above, so up to 24 joints the searching lanes' records go through LDS
+    // (24-joint chain, 2,000 x 256: 5.11 -> 3.81 ms, spills 188 -> 99
+    // registers; 20-joint streaming launch, 20,000 x 256: 69.1 -> 64.8 ms;
+    // 12 joints 2-3% faster; 16 joints at one wave per SIMD 4.93 -> 3.03 ms).
+    // At 32 joints (one wave, no spills) the shuffles measured faster (3.93 vs
+    // 4.09 ms).
+    static constexpr int ls = NM <= 24 ? kLsLds : kLsShfl;
 };
 
 // LDS of the line-search records of a workgroup of `threads` threads.
