@@ -76,6 +76,7 @@ def _robots():
     out["random32"] = W.random_chain(rng, 32)
     for c in (2, 3, 4):
         out[f"chained{6 * c}"] = W.chained_panda(c)
+    out["random16"] = W.random_chain(np.random.default_rng(16), 16)
     return out
 
 
@@ -414,6 +415,7 @@ def test_polish_line_search_lengths(H, ctx, ls_A, min_rows):
 LONG_CHAINS = {
     # name: (parameters, min rows compared CD, near, far)
     "random20": (dict(cd_sweeps=40, polish_iters=40), 0.76, 0.90, 0.78),
+    "random16": ({}, 0.92, 0.93, 0.90),
     "random24": ({}, 0.92, 0.92, 0.91),
     "random32": ({}, 0.93, 0.94, 0.94),
     "chained12": ({}, 0.95, 0.86, 0.88),
@@ -424,7 +426,7 @@ LONG_CHAINS = {
 
 @pytest.mark.parametrize("name", list(LONG_CHAINS))
 def test_long_chain_trajectories(H, ctx, name):
-    """The 12-, 20-, 24- and 32-joint buckets stage by stage: PO-CCD from
+    """The 12-, 16-, 20-, 24- and 32-joint buckets stage by stage: PO-CCD from
     uniform seeds, PJ-IK from seeds near the target and from uniform seeds
     (both occupancy variants of PJ-IK).  The 20-joint chain is the large
     configuration's robot at its 40 + 40 iterations."""
@@ -442,7 +444,7 @@ def test_long_chain_trajectories(H, ctx, name):
     _check_stage(H, ctx, rob, "polish", T=4, M=32, seed=22, params=params, min_rows=r_far)
 
 
-@pytest.mark.parametrize("name", ["random12", "chained18", "random20", "random24", "random32"])
+@pytest.mark.parametrize("name", ["random12", "random16", "chained18", "random20", "random24", "random32"])
 def test_cd_lane_pairs_bit_identical(H, ctx, name):
     """PO-CCD with two lanes per seed (each lane keeps half the joints'
     frames and candidates) takes the steps, draws and decisions of the
@@ -460,7 +462,7 @@ def test_cd_lane_pairs_bit_identical(H, ctx, name):
         assert a[4][kk] == b[4][kk], kk
 
 
-@pytest.mark.parametrize("name", ["panda", "random12", "random20", "random24", "random32"])
+@pytest.mark.parametrize("name", ["panda", "random12", "random16", "random20", "random24", "random32"])
 def test_polish_variants_bit_identical(H, ctx, name):
     """The two occupancy variants of the PJ-IK kernel compile the same device
     code: bit-identical configurations, errors and costs."""
