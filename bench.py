@@ -422,7 +422,7 @@ def _window_stats(info, mask, t0=None):
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 3), "span_s": round(span, 3)}
 
 
-def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, log):
+def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, pipes, log):
     """Poisson request streams: the continuous-batching server on the whole
     stream (warm-up + window; statistics over the requests that arrive in the
     window) and both modes on the stream's first `prefix` requests (the same
@@ -453,7 +453,8 @@ def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, log):
         if ri == 0:
             # kernel loading and first-touch allocation outside every measurement
             for mode in (H.HJCD_SERVE_BATCHED, H.HJCD_SERVE_PLAIN):
-                srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk)
+                srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk,
+                                           pipelines=pipes)
                 for i in range(min(n_req, 32)):
                     H.hjcd_server_submit(srv, poses[offs[i]:offs[i + 1]], int(s["seeds_per_target"][i]), int(offs[i]),
                                          0.0)
@@ -463,7 +464,7 @@ def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, log):
         infos = {}
         for mode, name, m in ((H.HJCD_SERVE_BATCHED, "served", n_req), (H.HJCD_SERVE_PLAIN, "plain", n_pre)):
             srv = H.hjcd_server_create(ctx, rb, sc, params, mode=mode, max_slots=slots, chunk_iters=chunk,
-                                       max_queue=m + 1)
+                                       max_queue=m + 1, pipelines=pipes)
             for i in range(m):
                 H.hjcd_server_submit(srv, poses[offs[i]:offs[i + 1]], int(s["seeds_per_target"][i]), int(offs[i]),
                                      float(s["arrival"][i]))
@@ -520,6 +521,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=1 << 22, help="resident seed slots of the server")
     ap.add_argument("--serve-chunk", type=int, default=20,
                     help="iterations per serving chunk (20 = a whole stage at the default iterations)")
+    ap.add_argument("--serve-pipelines", type=int, default=2,
+                    help="scheduler steps of the server in flight at once (1-4)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -575,7 +578,7 @@ def main():
         if args.headline_rate not in rates:
             rates.append(args.headline_rate)
         sv = serving(H, ctx, torch, rates, args.serve_window, args.serve_warmup, args.serve_prefix,
-                     args.serve_slots, args.serve_chunk, log)
+                     args.serve_slots, args.serve_chunk, args.serve_pipelines, log)
         head = next(r for r in sv if r["rate_req_s"] == args.headline_rate)
         line["value"] = head["served_window"]["solves_per_s"]
         line["p50_latency_ms"] = head["served_window"]["p50_latency_ms"]
@@ -588,7 +591,8 @@ def main():
                           "warmup_s": args.serve_warmup, "same_prefix_requests": head["same_prefix_requests"],
                           "dof": rob.dof, "link_spheres": int(rob.sphere_link.shape[0]),
                           "obstacle_spheres": int(batch.scene.spheres.shape[0]), "top_k": 1,
-                          "chunk_iters": args.serve_chunk, "max_slots": args.serve_slots,
+                          "chunk_iters": args.serve_chunk, "pipelines": args.serve_pipelines,
+                          "max_slots": args.serve_slots,
                           "cd_sweeps": 20, "polish_iters": 20, "scene": scene_note}
         line["serving"] = sv
     else:

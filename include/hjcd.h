@@ -383,7 +383,13 @@ typedef struct {
                               stage, the first PJ-IK chunk in the step that ends PO-CCD) gives the
                               lowest latency, shorter chunks retire targets at more points */
     int32_t max_queue;     /* pending requests accepted before submit returns HJCD_E_BUSY */
+    int32_t pipelines;     /* scheduler steps in flight at once, 1..HJCD_SERVE_MAX_PIPELINES (0 = 2):
+                              each has its own stream and keeps the requests it admitted; a request
+                              that arrives while steps run starts on a free one.  More pipelines
+                              lower latency at high load and raise it at light load */
 } hjcd_server_config;
+
+#define HJCD_SERVE_MAX_PIPELINES 4
 
 typedef struct {
     int64_t request_id;

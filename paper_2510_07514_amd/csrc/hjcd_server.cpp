@@ -43,6 +43,7 @@ struct Request {
     int32_t tbl0 = -1;
     int stage = SERVE_CD;
     int iter = 0;
+    bool fuse = false;  // this step ends its PO-CCD and runs its first PJ-IK chunk
     // results
     std::vector<int32_t> status;  // per target: 0 running, 1 solved, 2 finished
     std::vector<float> res;       // [n_targets][n + 3]
@@ -105,13 +106,24 @@ struct hjcd_server_s {
     ServeState st{};
     float* d_pose = nullptr;
     uint32_t* d_tkey = nullptr;
-    // per-chunk transfers: one host-to-device upload of every list the
-    // chunk's kernels read, one device-to-host readback of the decisions
-    char* d_up = nullptr;
-    char* h_up = nullptr;
+    // step pipelines: each has its stream, its per-step transfers (one
+    // host-to-device upload of every list the step's kernels read, one
+    // device-to-host readback of the decisions), its requests and the event
+    // of its step in flight.  A request stays with the pipeline that admitted
+    // it; pipelines run their steps concurrently, so a request that arrives
+    // while one step runs starts on a free pipeline instead of waiting.
+    struct Pipe {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr;
+        char* d_up = nullptr;
+        char* h_up = nullptr;
+        char* d_down = nullptr;
+        char* h_down = nullptr;
+        bool busy = false;
+        std::vector<std::unique_ptr<Request>> active;
+    };
+    std::vector<Pipe> pipes;  // hjcd_server_config::pipelines of them (batched mode)
     size_t up_cap = 0;
-    char* d_down = nullptr;
-    char* h_down = nullptr;
     size_t down_cap = 0;
     // plain mode staging
     float* h_pose = nullptr;
@@ -128,7 +140,6 @@ struct hjcd_server_s {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<std::unique_ptr<Request>> pending;  // by arrival
-    std::vector<std::unique_ptr<Request>> active;
     std::map<int64_t, std::unique_ptr<Request>> finished;
     std::deque<int64_t> unpolled;
     std::vector<double> latencies;
@@ -171,12 +182,20 @@ hjcd_status server_alloc_batched(hjcd_server s) {
                 3 * align16(sizeof(ServeBlock) * nb_max) + align16(sizeof(int32_t) * nb_max) +
                 3 * align16(sizeof(int32_t) * Tc) + align16(sizeof(int64_t) * Tc);
     s->down_cap = align16(sizeof(int32_t) * Tc) + align16(sizeof(float) * Tc * (s->n + 3));
-    s->d_up = dev_alloc<char>(s->up_cap, ok);
-    s->d_down = dev_alloc<char>(s->down_cap, ok);
+    s->pipes.resize(s->cfg.pipelines);
+    for (auto& P : s->pipes) {
+        P.d_up = dev_alloc<char>(s->up_cap, ok);
+        P.d_down = dev_alloc<char>(s->down_cap, ok);
+    }
     if (!ok) return fail(HJCD_E_NOMEM, "server device allocation failed (%lld slots)", (long long)C);
-    if (hipHostMalloc((void**)&s->h_up, s->up_cap, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_down, s->down_cap, hipHostMallocDefault) != hipSuccess)
-        return fail(HJCD_E_NOMEM, "server pinned host allocation failed");
+    for (auto& P : s->pipes) {
+        if (hipHostMalloc((void**)&P.h_up, s->up_cap, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&P.h_down, s->down_cap, hipHostMallocDefault) != hipSuccess)
+            return fail(HJCD_E_NOMEM, "server pinned host allocation failed");
+        if (hipStreamCreateWithFlags(&P.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&P.done, hipEventDisableTiming) != hipSuccess)
+            return fail(HJCD_E_DEVICE, "server stream creation failed");
+    }
     // every slot starts dead
     HIP_TRY(hipMemsetAsync(s->st.sstate, 0, C, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -186,13 +205,21 @@ hjcd_status server_alloc_batched(hjcd_server s) {
 }
 
 void server_free(hjcd_server s) {
-    void* dptr[] = {s->st.q,   s->st.sstate, s->st.slot_target, s->st.slot_m, s->st.err_p, s->st.err_o,
-                    s->st.cost, s->d_pose,   s->d_tkey,         s->d_up,       s->d_down,   s->p_targets,
-                    s->p_q,    s->p_ep,      s->p_eo,           s->p_fl,       s->p_sv,     s->p_nf,
-                    s->p_keys};
+    for (auto& P : s->pipes) {
+        if (P.stream) (void)hipStreamSynchronize(P.stream);
+        if (P.d_up) (void)hipFree(P.d_up);
+        if (P.d_down) (void)hipFree(P.d_down);
+        if (P.h_up) (void)hipHostFree(P.h_up);
+        if (P.h_down) (void)hipHostFree(P.h_down);
+        if (P.done) (void)hipEventDestroy(P.done);
+        if (P.stream) (void)hipStreamDestroy(P.stream);
+    }
+    void* dptr[] = {s->st.q,    s->st.sstate, s->st.slot_target, s->st.slot_m, s->st.err_p, s->st.err_o,
+                    s->st.cost, s->d_pose,    s->d_tkey,         s->p_targets, s->p_q,     s->p_ep,
+                    s->p_eo,    s->p_fl,      s->p_sv,           s->p_nf,      s->p_keys};
     for (void* p : dptr)
         if (p) (void)hipFree(p);
-    void* hptr[] = {s->h_up, s->h_down, s->h_pose, s->h_tkey};
+    void* hptr[] = {s->h_pose, s->h_tkey};
     for (void* p : hptr)
         if (p) (void)hipHostFree(p);
     if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -228,13 +255,16 @@ struct Arena {
     }
 };
 
-hjcd_status batched_step(hjcd_server s) {
+// Launches one step of pipeline P: admits the arrived requests that fit
+// (they join P), uploads the step's lists and enqueues its kernels and the
+// decision readback on P's stream, then records P's event.  Nothing waits.
+hjcd_status launch_step(hjcd_server s, hjcd_server_s::Pipe& P) {
     const int n = s->n;
     const hjcd_params& p = s->params;
     const int c = s->cfg.chunk_iters;
     const int64_t nb_max = s->C / 64;
     const int32_t Tc = s->Tc;
-    Arena ar{s->h_up, s->d_up};
+    Arena ar{P.h_up, P.d_up};
     ServeAdmit* d_adm;
     float* d_upose;
     ServeAdmit* h_adm = ar.take<ServeAdmit>(Tc, &d_adm);
@@ -266,11 +296,11 @@ hjcd_status batched_step(hjcd_server s) {
                                         target_key(r->tag, 0)};
             n_up += r->n_targets;
             s->stats.admitted++;
-            s->active.push_back(std::move(s->pending.front()));
+            P.active.push_back(std::move(s->pending.front()));
             s->pending.pop_front();
         }
     }
-    if (s->active.empty()) return HJCD_OK;
+    if (P.active.empty()) return HJCD_OK;
 
     // 2. the chunk's lists: every resident block at its stage's next
     //    iterations; the blocks whose PO-CCD ends in this chunk again, for
@@ -285,10 +315,14 @@ hjcd_status batched_step(hjcd_server s) {
     };
     int32_t nb = 0, nb2 = 0, nchk = 0, nt = 0;
     int64_t resident = 0;
-    for (auto& up : s->active) {
+    for (auto& Q : s->pipes)
+        if (&Q != &P && Q.busy)
+            for (auto& up : Q.active) resident += (int64_t)up->nblocks * 64;
+    for (auto& up : P.active) {
         resident += (int64_t)up->nblocks * 64;
         nb += up->nblocks;
         const bool fuse = cd_ends(up.get());
+        up->fuse = fuse;
         if (fuse) nb2 += up->nblocks;
         if (up->stage == SERVE_POLISH || fuse) {
             nchk += up->nblocks;
@@ -309,10 +343,10 @@ hjcd_status batched_step(hjcd_server s) {
     int32_t* h_rfinal = ar.take<int32_t>(nt, &d_rfinal);
     if (ar.off > s->up_cap) return fail(HJCD_E_INTERNAL, "serving upload arena overflow");
     int32_t ib = 0, ib2 = 0, ic = 0, it = 0;
-    for (auto& up : s->active) {
+    for (auto& up : P.active) {
         Request* r = up.get();
         const bool cd = r->stage == SERVE_CD;
-        const bool fuse = cd_ends(r);
+        const bool fuse = r->fuse;
         const int len = cd ? p.cd_sweeps : p.polish_iters;
         const int k0 = r->iter, k1 = std::min(r->iter + c, len);
         // this step's PJ-IK iterations: the stage's next chunk, or its first
@@ -338,8 +372,8 @@ hjcd_status batched_step(hjcd_server s) {
             it++;
         }
     }
-    HIP_TRY(hipMemcpyAsync(s->d_up, s->h_up, ar.off, hipMemcpyHostToDevice, s->stream));
-    if (n_adm > 0) HIP_TRY(launch_serve_admit(d_adm, n_adm, d_upose, s->d_pose, s->d_tkey, s->st, s->stream));
+    HIP_TRY(hipMemcpyAsync(P.d_up, P.h_up, ar.off, hipMemcpyHostToDevice, P.stream));
+    if (n_adm > 0) HIP_TRY(launch_serve_admit(d_adm, n_adm, d_upose, s->d_pose, s->d_tkey, s->st, P.stream));
 
     ServeChunkArgs ca{};
     ca.rb = s->robot->dev;
@@ -348,12 +382,12 @@ hjcd_status batched_step(hjcd_server s) {
     ca.blocks = d_blk;
     ca.nb = nb;
     ca.kp = kparams(p);
-    HIP_TRY(launch_serve_chunk(ca, s->stream));
+    HIP_TRY(launch_serve_chunk(ca, P.stream));
     if (nb2 > 0) {  // first PJ-IK chunk of the requests whose PO-CCD just ended
         ServeChunkArgs c2 = ca;
         c2.blocks = d_blk2;
         c2.nb = nb2;
-        HIP_TRY(launch_serve_chunk(c2, s->stream));
+        HIP_TRY(launch_serve_chunk(c2, P.stream));
     }
     if (nchk > 0) {
         ServeCheckArgs ck{};
@@ -368,10 +402,10 @@ hjcd_status batched_step(hjcd_server s) {
         ck.obox = s->scene ? s->scene->box : nullptr;
         ck.n_obox = s->scene ? s->scene->n_box : 0;
         ck.grid = scene_grid(s->scene, s->robot);
-        HIP_TRY(launch_serve_check(ck, s->stream));
+        HIP_TRY(launch_serve_check(ck, P.stream));
     }
-    int32_t* h_status = (int32_t*)s->h_down;
-    float* h_res = (float*)(s->h_down + align16(sizeof(int32_t) * Tc));
+    int32_t* h_status = (int32_t*)P.h_down;
+    float* h_res = (float*)(P.h_down + align16(sizeof(int32_t) * Tc));
     if (nt > 0) {
         ServeReduceArgs ra{};
         ra.st = s->st;
@@ -383,23 +417,45 @@ hjcd_status batched_step(hjcd_server s) {
         ra.nt = nt;
         ra.succ_pos = p.succ_pos;
         ra.succ_ori = p.succ_ori;
-        ra.status = (int32_t*)s->d_down;
-        ra.res = (float*)(s->d_down + align16(sizeof(int32_t) * Tc));
-        HIP_TRY(launch_serve_reduce(ra, s->stream));
+        ra.status = (int32_t*)P.d_down;
+        ra.res = (float*)(P.d_down + align16(sizeof(int32_t) * Tc));
+        HIP_TRY(launch_serve_reduce(ra, P.stream));
         // status rows, then result rows (contiguous from the arena start up to nt rows)
-        HIP_TRY(hipMemcpyAsync(h_status, s->d_down, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, s->stream));
-        HIP_TRY(hipMemcpyAsync(h_res, ra.res, sizeof(float) * nt * (n + 3), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(h_status, P.d_down, sizeof(int32_t) * nt, hipMemcpyDeviceToHost, P.stream));
+        HIP_TRY(hipMemcpyAsync(h_res, ra.res, sizeof(float) * nt * (n + 3), hipMemcpyDeviceToHost, P.stream));
     }
-    HIP_TRY(hipStreamSynchronize(s->stream));
+    HIP_TRY(hipEventRecord(P.done, P.stream));
+    P.busy = true;
+    {
+        // the statistics are read under the same mutex by hjcd_server_get_stats
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->stats.chunks++;
+        s->resident_sum += (double)resident;
+        s->stats.resident_slots_peak = std::max<int64_t>(s->stats.resident_slots_peak, resident);
+    }
+    return HJCD_OK;
+}
+
+// Completes pipeline P's step once its event has passed: records finished
+// targets (from the readback), advances stages, completes requests whose
+// targets are all finished (their slots return to the pool).
+hjcd_status finish_step(hjcd_server s, hjcd_server_s::Pipe& P) {
+    const int n = s->n;
+    const hjcd_params& p = s->params;
+    const int c = s->cfg.chunk_iters;
+    const int32_t Tc = s->Tc;
+    const int32_t* h_status = (const int32_t*)P.h_down;
+    const float* h_res = (const float*)(P.h_down + align16(sizeof(int32_t) * Tc));
+    P.busy = false;
     const double t_done = s->now();
+    int32_t it = 0;
 
     // 3. bookkeeping: results, stage transitions, completions
-    it = 0;
     std::vector<std::unique_ptr<Request>> keep;
     std::vector<std::unique_ptr<Request>> done;
-    for (auto& up : s->active) {
+    for (auto& up : P.active) {
         Request* r = up.get();
-        const bool fuse = cd_ends(r);
+        const bool fuse = r->fuse;
         if (r->stage == SERVE_POLISH || fuse) {
             for (int k = 0; k < r->n_targets; ++k) {
                 if (r->status[k] != 0) continue;
@@ -429,13 +485,9 @@ hjcd_status batched_step(hjcd_server s) {
             keep.push_back(std::move(up));
         }
     }
-    s->active.swap(keep);
+    P.active.swap(keep);
     {
-        // the statistics are read under the same mutex by hjcd_server_get_stats
         std::unique_lock<std::mutex> lk(s->mu);
-        s->stats.chunks++;
-        s->resident_sum += (double)resident;
-        s->stats.resident_slots_peak = std::max<int64_t>(s->stats.resident_slots_peak, resident);
         for (auto& r : done) finish_request(s, std::move(r));
     }
     return HJCD_OK;
@@ -505,25 +557,83 @@ hjcd_status plain_step(hjcd_server s) {
     return HJCD_OK;
 }
 
+// One scheduler pass of the batched server: completes the steps whose events
+// have passed, then launches a step on a free pipeline that has requests or
+// can admit arrived ones.  Sets `progressed` when it did either.
+hjcd_status batched_pass(hjcd_server s, bool& progressed, bool& any_busy) {
+    progressed = false;
+    for (auto& P : s->pipes) {
+        if (!P.busy) continue;
+        const hipError_t e = hipEventQuery(P.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return fail(HJCD_E_DEVICE, "serving step failed: %s", hipGetErrorString(e));
+        hjcd_status st = finish_step(s, P);
+        if (st != HJCD_OK) return st;
+        progressed = true;
+    }
+    bool arrived;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        arrived = !s->pending.empty() && s->pending.front()->arrival <= s->now();
+    }
+    for (auto& P : s->pipes) {
+        if (P.busy || (P.active.empty() && !arrived)) continue;
+        hjcd_status st = launch_step(s, P);
+        if (st != HJCD_OK) return st;
+        if (P.busy) {
+            progressed = true;
+            break;  // one launch per pass; the next pass sees the new arrivals
+        }
+    }
+    any_busy = false;
+    for (auto& P : s->pipes) any_busy = any_busy || P.busy;
+    return HJCD_OK;
+}
+
 void worker_main(hjcd_server s) {
     (void)hipSetDevice(s->device);
+    const bool plain = s->cfg.mode == HJCD_SERVE_PLAIN;
     while (!s->stop.load()) {
-        bool idle;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            idle = s->active.empty() && (s->pending.empty() || s->pending.front()->arrival > s->now());
-            if (idle) {
-                if (s->pending.empty()) {
-                    s->cv.wait_for(lk, std::chrono::milliseconds(50));
+        hjcd_status st = HJCD_OK;
+        if (!plain) {
+            bool progressed = false, any_busy = false;
+            st = batched_pass(s, progressed, any_busy);
+            if (st == HJCD_OK && !progressed) {
+                if (any_busy) {
+                    // a step is in flight: poll its event again shortly
+                    std::this_thread::sleep_for(std::chrono::microseconds(10));
                 } else {
-                    const double dt = s->pending.front()->arrival - s->now();
-                    if (dt > 0)
-                        s->cv.wait_for(lk, std::chrono::microseconds((int64_t)std::min(dt * 1e6, 5e4)));
+                    std::unique_lock<std::mutex> lk(s->mu);
+                    bool resident = false;
+                    for (auto& P : s->pipes) resident = resident || !P.active.empty();
+                    if (!resident) {
+                        if (s->pending.empty()) {
+                            s->cv.wait_for(lk, std::chrono::milliseconds(50));
+                        } else {
+                            const double dt = s->pending.front()->arrival - s->now();
+                            if (dt > 0)
+                                s->cv.wait_for(lk, std::chrono::microseconds((int64_t)std::min(dt * 1e6, 5e4)));
+                        }
+                    }
                 }
-                continue;
             }
+        } else {
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                const bool idle = s->pending.empty() || s->pending.front()->arrival > s->now();
+                if (idle) {
+                    if (s->pending.empty()) {
+                        s->cv.wait_for(lk, std::chrono::milliseconds(50));
+                    } else {
+                        const double dt = s->pending.front()->arrival - s->now();
+                        if (dt > 0)
+                            s->cv.wait_for(lk, std::chrono::microseconds((int64_t)std::min(dt * 1e6, 5e4)));
+                    }
+                    continue;
+                }
+            }
+            st = plain_step(s);
         }
-        hjcd_status st = s->cfg.mode == HJCD_SERVE_PLAIN ? plain_step(s) : batched_step(s);
         if (st != HJCD_OK) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->worker_error = hjcd_last_error();
@@ -550,6 +660,8 @@ hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene,
     if (config->chunk_iters < 1) return fail(HJCD_E_INVALID, "chunk_iters must be >= 1");
     if (config->max_slots < 0 || config->max_targets < 0 || config->max_queue < 0)
         return fail(HJCD_E_INVALID, "server sizes must be >= 0");
+    if (config->pipelines < 0 || config->pipelines > HJCD_SERVE_MAX_PIPELINES)
+        return fail(HJCD_E_INVALID, "pipelines must be in 0..%d", HJCD_SERVE_MAX_PIPELINES);
     if (params->polish_iters < 1) return fail(HJCD_E_UNSUPPORTED, "serving needs polish_iters >= 1");
     if (params->resample_K > 0) return fail(HJCD_E_UNSUPPORTED, "serving does not resample between stages");
     if (!ctx) return fail(HJCD_E_INVALID, "ctx is NULL");
@@ -578,6 +690,7 @@ hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene,
     srv->params = *params;
     srv->cfg = *config;
     if (srv->cfg.max_queue == 0) srv->cfg.max_queue = 1 << 22;
+    if (srv->cfg.pipelines == 0) srv->cfg.pipelines = 2;
     srv->n = robot->n;
     if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
         delete srv;
@@ -746,6 +859,8 @@ void hjcd_server_destroy(hjcd_server srv) {
     if (srv->worker.joinable()) srv->worker.join();
     (void)hipSetDevice(srv->device);
     if (srv->stream) (void)hipStreamSynchronize(srv->stream);
+    for (auto& P : srv->pipes)
+        if (P.stream) (void)hipStreamSynchronize(P.stream);
     server_free(srv);
     delete srv;
 }

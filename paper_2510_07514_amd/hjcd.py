@@ -98,7 +98,8 @@ class hjcd_tune_choice(C.Structure):
 
 class hjcd_server_config(C.Structure):
     _fields_ = [("mode", C.c_int32), ("max_slots", C.c_int64), ("hbm_budget", C.c_size_t),
-                ("max_targets", C.c_int32), ("chunk_iters", C.c_int32), ("max_queue", C.c_int32)]
+                ("max_targets", C.c_int32), ("chunk_iters", C.c_int32), ("max_queue", C.c_int32),
+                ("pipelines", C.c_int32)]
 
 
 class hjcd_request_info(C.Structure):
@@ -534,8 +535,8 @@ class Server:
 
 
 def hjcd_server_create(ctx, robot, scene, params, mode=HJCD_SERVE_BATCHED, max_slots=0, hbm_budget=0,
-                       max_targets=0, chunk_iters=20, max_queue=0) -> Server:
-    cfg = hjcd_server_config(mode, max_slots, hbm_budget, max_targets, chunk_iters, max_queue)
+                       max_targets=0, chunk_iters=20, max_queue=0, pipelines=0) -> Server:
+    cfg = hjcd_server_config(mode, max_slots, hbm_budget, max_targets, chunk_iters, max_queue, pipelines)
     h = _vp()
     _check(_lib.hjcd_server_create(ctx.handle, robot.handle, scene.handle if scene else None, C.byref(params),
                                    C.byref(cfg), C.byref(h)))

@@ -152,3 +152,41 @@ def test_scene_and_stage_validation(H):
     assert H._lib.hjcd_resample(None, None, 1, offs.ctypes.data, None, C.byref(p), None, None, None,
                                 None) == H.HJCD_E_INVALID
     assert "resample_K" in H.hjcd_last_error()
+
+
+def test_struct_layouts_match_the_header(H, tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct of the same name."""
+    structs = [H.hjcd_robot_desc, H.hjcd_params, H.hjcd_stats, H.hjcd_tune_choice, H.hjcd_server_config,
+               H.hjcd_request_info, H.hjcd_server_stats]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hjcd.h"', "int main(void) {"]
+    for S in structs:
+        lines.append(f'  printf("{S.__name__} %zu\\n", sizeof({S.__name__}));')
+        for f in S._fields_:
+            lines.append(f'  printf("{S.__name__}.{f[0]} %zu\\n", offsetof({S.__name__}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for S in structs:
+        assert int(got[S.__name__]) == C.sizeof(S), S.__name__
+        for f in S._fields_:
+            assert int(got[f"{S.__name__}.{f[0]}"]) == getattr(S, f[0]).offset, (S.__name__, f[0])
+
+
+def test_server_config_validation_before_device(H):
+    """Server configuration errors are reported before the context is used."""
+    p = H.hjcd_params_default()
+    h = C.c_void_p()
+    for kw, status in [(dict(chunk_iters=0), H.HJCD_E_INVALID), (dict(mode=7), H.HJCD_E_INVALID),
+                       (dict(pipelines=-1), H.HJCD_E_INVALID), (dict(pipelines=5), H.HJCD_E_INVALID),
+                       (dict(max_queue=-1), H.HJCD_E_INVALID)]:
+        cfg = H.hjcd_server_config(**dict(dict(chunk_iters=20), **kw))
+        assert H._lib.hjcd_server_create(None, None, None, C.byref(p), C.byref(cfg), C.byref(h)) == status, kw
+    cfg = H.hjcd_server_config(chunk_iters=20, pipelines=4)
+    assert H._lib.hjcd_server_create(None, None, None, C.byref(p), C.byref(cfg), C.byref(h)) == H.HJCD_E_INVALID
+    assert "ctx" in H.hjcd_last_error()

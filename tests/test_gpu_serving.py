@@ -85,13 +85,19 @@ def test_serve_alone_equals_mix(H, ctx):
     mix, info_m, st_m = _serve(H, ctx, rb, sc, params, reqs, chunk_iters=3, max_slots=1 << 14)
     small = max(((len(r["targets"]) * r["M"] + 63) // 64) * 64 for r in reqs)
     tight, info_t, st_t = _serve(H, ctx, rb, sc, params, reqs, chunk_iters=3, max_slots=small + 64)
-    say(f"  chunks alone {st_a['chunks']} mix {st_m['chunks']} tight {st_t['chunks']}; "
+    # arrivals spread over the steps, on one pipeline and on four (requests
+    # admitted while other steps run start on the free pipelines)
+    arr = np.arange(len(reqs)) * 2e-4
+    one, _, st_1 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=1)
+    four, _, st_4 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=4)
+    say(f"  chunks alone {st_a['chunks']} mix {st_m['chunks']} tight {st_t['chunks']} "
+        f"staggered on 1 / 4 pipelines {st_1['chunks']} / {st_4['chunks']}; "
         f"peak slots mix {st_m['resident_slots_peak']} tight {st_t['resident_slots_peak']} (pool {st_t['max_slots']})")
     for i, r in enumerate(reqs):
-        for other in (mix[i], tight[i]):
+        for other in (mix[i], tight[i], one[i], four[i]):
             for key in ("q", "err_p", "err_o", "flag"):
                 assert np.array_equal(alone[i][key], other[key]), (i, key)
-    assert st_m["completed"] == len(reqs) and st_t["completed"] == len(reqs)
+    assert all(st["completed"] == len(reqs) for st in (st_m, st_t, st_1, st_4))
     assert st_t["resident_slots_peak"] <= st_t["max_slots"]
     # the mixed run really overlapped requests on the device
     assert st_m["resident_slots_peak"] > small
