@@ -482,7 +482,8 @@ def serving(H, ctx, torch, rates, window, warm, prefix, slots, chunk, pipes, log
                 row["served_window"] = dict(_window_stats(info, info["arrival_s"] >= warm, t0=warm),
                                             chunks=int(st["chunks"]),
                                             mean_resident_slots=round(st["mean_resident_slots"], 1),
-                                            resident_slots_peak=int(st["resident_slots_peak"]))
+                                            resident_slots_peak=int(st["resident_slots_peak"]),
+                                            overlapped_steps=int(st["overlapped_steps"]))
         pre = np.arange(n_req) < n_pre
         row["served_same_prefix"] = _window_stats(infos["served"], pre)
         row["plain_same_prefix"] = _window_stats(infos["plain"], np.ones(infos["plain"].shape[0], bool))

@@ -407,6 +407,7 @@ typedef struct {
     double p50_latency_ms, p99_latency_ms;  /* done - arrival over completed requests */
     double first_arrival_s, last_done_s;
     double solves_per_s;   /* targets_solved / (last_done - first_arrival) */
+    int64_t overlapped_steps;  /* steps launched while another pipeline's step was in flight */
 } hjcd_server_stats;
 
 hjcd_status hjcd_server_create(hjcd_ctx ctx, hjcd_robot robot, hjcd_scene scene /* nullable */,

@@ -425,11 +425,14 @@ hjcd_status launch_step(hjcd_server s, hjcd_server_s::Pipe& P) {
         HIP_TRY(hipMemcpyAsync(h_res, ra.res, sizeof(float) * nt * (n + 3), hipMemcpyDeviceToHost, P.stream));
     }
     HIP_TRY(hipEventRecord(P.done, P.stream));
+    bool overlapped = false;  // another pipeline's step is in flight
+    for (const auto& Q : s->pipes) overlapped = overlapped || (&Q != &P && Q.busy);
     P.busy = true;
     {
         // the statistics are read under the same mutex by hjcd_server_get_stats
         std::unique_lock<std::mutex> lk(s->mu);
         s->stats.chunks++;
+        if (overlapped) s->stats.overlapped_steps++;
         s->resident_sum += (double)resident;
         s->stats.resident_slots_peak = std::max<int64_t>(s->stats.resident_slots_peak, resident);
     }

@@ -117,7 +117,7 @@ class hjcd_server_stats(C.Structure):
                 ("max_slots", C.c_int64), ("resident_slots_peak", C.c_int64),
                 ("mean_resident_slots", C.c_double), ("p50_latency_ms", C.c_double),
                 ("p99_latency_ms", C.c_double), ("first_arrival_s", C.c_double),
-                ("last_done_s", C.c_double), ("solves_per_s", C.c_double)]
+                ("last_done_s", C.c_double), ("solves_per_s", C.c_double), ("overlapped_steps", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

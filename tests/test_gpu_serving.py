@@ -91,7 +91,8 @@ def test_serve_alone_equals_mix(H, ctx):
     one, _, st_1 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=1)
     four, _, st_4 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=4)
     say(f"  chunks alone {st_a['chunks']} mix {st_m['chunks']} tight {st_t['chunks']} "
-        f"staggered on 1 / 4 pipelines {st_1['chunks']} / {st_4['chunks']}; "
+        f"staggered on 1 / 4 pipelines {st_1['chunks']} / {st_4['chunks']} "
+        f"(overlapped {st_1['overlapped_steps']} / {st_4['overlapped_steps']}); "
         f"peak slots mix {st_m['resident_slots_peak']} tight {st_t['resident_slots_peak']} (pool {st_t['max_slots']})")
     for i, r in enumerate(reqs):
         for other in (mix[i], tight[i], one[i], four[i]):
@@ -102,6 +103,8 @@ def test_serve_alone_equals_mix(H, ctx):
     # the mixed run really overlapped requests on the device
     assert st_m["resident_slots_peak"] > small
     assert st_m["chunks"] < st_a["chunks"]
+    # one pipeline never overlaps steps; four did, and gave the same results
+    assert st_1["overlapped_steps"] == 0 and st_4["overlapped_steps"] > 0
 
 
 # Cost 0.5 (|r_p|^2 + phi^2) below which seeds have converged to single
