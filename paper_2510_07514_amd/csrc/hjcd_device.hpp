@@ -197,12 +197,23 @@ __device__ __forceinline__ void chain_step(const DevRobot* __restrict__ rb, int 
     }
 }
 
+// a / b for finite b of moderate size (|b| in [2^-100, 2^100]): the hardware
+// reciprocal estimate (1 ulp), the quotient, and one correction with the
+// exact FMA residual a - q b (Markstein, IA-64 and Elementary Functions,
+// 2000), which leaves the quotient within about half an ulp.
+__device__ __forceinline__ float div_corr(float a, float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    const float q = a * r;
+    return fmaf(fmaf(-q, b, a), r, q);
+}
+
 // Rotation -> unit quaternion, Shepperd's method (largest of trace and the
-// diagonal decides the divisor), w >= 0.  FAST: hardware square root and
-// reciprocal (1 ulp), for the collision pass's compressed link frames (a
-// residual fed to the solver's decisions keeps the correctly rounded forms:
-// a 2-4 ulp residual moved one sensitive PJ-IK trajectory out of the 1e-4
-// band).
+// diagonal decides the divisor), w >= 0; the divisor 4 max(w^2, x^2, y^2,
+// z^2) lies in [1, 4].  FAST: hardware square root and reciprocal (1 ulp),
+// for the collision pass's compressed link frames.  A residual fed to the
+// solver's decisions keeps the correctly rounded square root and the
+// corrected quotient (half an ulp): a 2-4 ulp residual moved one sensitive
+// PJ-IK trajectory out of the 1e-4 band.
 // CANON = false skips the final sign choice (q and -q are the same rotation);
 // the cost of a trial only needs |w| and |v| of the error quaternion, which do
 // not depend on that sign.
@@ -219,7 +230,7 @@ __device__ __forceinline__ Quat quat_of(const Frame& F) {
                                                                        : 1.f - R00 - R11 + R22;
     const float r = FAST ? __builtin_amdgcn_sqrtf(big) : sqrtf(big);
     const float qb = 0.5f * r;
-    const float k = FAST ? 0.5f * __builtin_amdgcn_rcpf(r) : 0.5f / r;
+    const float k = FAST ? 0.5f * __builtin_amdgcn_rcpf(r) : div_corr(0.5f, r);
     const float d21 = (R21 - R12) * k, d02 = (R02 - R20) * k, d10 = (R10 - R01) * k;
     const float s01 = (R01 + R10) * k, s02 = (R02 + R20) * k, s12 = (R12 + R21) * k;
     Quat q;
@@ -1016,7 +1027,7 @@ __device__ __forceinline__ double rsqrt_nr(double s) {
 }
 
 __device__ __forceinline__ double rcp_nr(double d) {
-    double r = (double)(1.f / (float)d);
+    double r = (double)__builtin_amdgcn_rcpf((float)d);
     r = r * fma(-d, r, 2.0);
     r = r * fma(-d, r, 2.0);
     return r;
@@ -1454,7 +1465,7 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
                 }
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
-                    w6[r] = kp.weight_mode == 0 ? 1.f / fmaxf(sqrtf(rn[r]), 1e-6f) : 1.f;
+                    w6[r] = kp.weight_mode == 0 ? div_corr(1.f, fmaxf(sqrtf(rn[r]), 1e-6f)) : 1.f;
                 // A = W (sum_j J_j J_j^T / D_j) W + lam I,  D_j = |J_j|^2 (double)
                 double A[21];
 #pragma unroll
@@ -1505,7 +1516,7 @@ __device__ __forceinline__ void pj_ik_iter(RobotRef rb, int n, const Target& tg,
                             dj = fmaf(c[r], c[r], dj);
                             g = fmaf(c[r], y[r], g);
                         }
-                        dth[j] = clampf(g / dj, -R, R);  // trust region, elementwise
+                        dth[j] = clampf(div_corr(g, dj), -R, R);  // trust region, elementwise
                     }
                 }
             }
