@@ -73,7 +73,8 @@ def _load(H, ctx, rob, scene):
 def test_serve_alone_equals_mix(H, ctx):
     """Each request's served result is bit-identical whether it runs alone or
     batched with others (all arriving together, and under a slot pool small
-    enough that requests wait for admission)."""
+    enough that requests wait for admission), and on one or four step
+    pipelines with staggered arrivals."""
     say("case: serving alone vs mix")
     s = W.serving_stream(1000.0, 0.01)
     rob, scene = s["robot"], s["scene"]
@@ -90,16 +91,22 @@ def test_serve_alone_equals_mix(H, ctx):
     arr = np.arange(len(reqs)) * 2e-4
     one, _, st_1 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=1)
     four, _, st_4 = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=1 << 14, pipelines=4)
+    # four pipelines sharing a pool that holds about two requests: admission waits for slots
+    # that another pipeline's requests free
+    four_t, _, st_4t = _serve(H, ctx, rb, sc, params, reqs, arrivals=arr, chunk_iters=3, max_slots=2 * small + 64,
+                              pipelines=4)
     say(f"  chunks alone {st_a['chunks']} mix {st_m['chunks']} tight {st_t['chunks']} "
         f"staggered on 1 / 4 pipelines {st_1['chunks']} / {st_4['chunks']} "
-        f"(overlapped {st_1['overlapped_steps']} / {st_4['overlapped_steps']}); "
+        f"(overlapped {st_1['overlapped_steps']} / {st_4['overlapped_steps']}), tight on 4 {st_4t['chunks']} "
+        f"(overlapped {st_4t['overlapped_steps']}); "
         f"peak slots mix {st_m['resident_slots_peak']} tight {st_t['resident_slots_peak']} (pool {st_t['max_slots']})")
     for i, r in enumerate(reqs):
-        for other in (mix[i], tight[i], one[i], four[i]):
+        for other in (mix[i], tight[i], one[i], four[i], four_t[i]):
             for key in ("q", "err_p", "err_o", "flag"):
                 assert np.array_equal(alone[i][key], other[key]), (i, key)
-    assert all(st["completed"] == len(reqs) for st in (st_m, st_t, st_1, st_4))
+    assert all(st["completed"] == len(reqs) for st in (st_m, st_t, st_1, st_4, st_4t))
     assert st_t["resident_slots_peak"] <= st_t["max_slots"]
+    assert st_4t["resident_slots_peak"] <= st_4t["max_slots"]
     # the mixed run really overlapped requests on the device
     assert st_m["resident_slots_peak"] > small
     assert st_m["chunks"] < st_a["chunks"]
