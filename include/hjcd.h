@@ -327,7 +327,8 @@ typedef struct hjcd_plan_s* hjcd_plan;
 typedef struct {
     int32_t variant;        /* PJ-IK occupancy: 0 default, 1 the alternative (waves per SIMD
                                0 / 1: 3 / 2 up to 8 joints, 2 / 1 up to 24, 1 / 2 above) */
-    int32_t block_threads;  /* workgroup size of the per-seed kernel */
+    int32_t block_threads;  /* workgroup size of the PJ-IK kernel (64 without tuning, as in
+                               hjcd_solve; PO-CCD runs 256-thread workgroups) */
     float ms;               /* measured time of the chosen PJ-IK shape (0 when not tuned) */
     int64_t seeds;          /* seeds of this robot in the batch */
     int32_t cd_lanes;       /* PO-CCD lanes per seed chosen (1 or 2) */

@@ -351,7 +351,7 @@ hjcd_status hjcd_plan_create(hjcd_ctx c, int32_t n_robots, const hjcd_robot* rob
     group_targets(n_robots, T, robot_of_target, offs, p->grp);
     for (int ri = 0; ri < n_robots; ++ri) {
         p->choice[ri].variant = params->polish_variant;
-        p->choice[ri].block_threads = 256;
+        p->choice[ri].block_threads = 64;  // hjcd_solve's PJ-IK default
         p->choice[ri].cd_lanes = robots[ri]->n >= 9 && params->cd_lanes_per_seed == 2 ? 2 : 1;
         p->choice[ri].cd_ms = 0.f;
         p->choice[ri].ms = 0.f;
