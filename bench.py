@@ -78,13 +78,23 @@ def measured_traffic():
 
 
 def cpu_model():
+    """Host CPU as /proc/cpuinfo names it: the model string plus family, model
+    and stepping numbers (a virtualised host may report only a brand name, and
+    the numbers still identify the core generation) and the visible threads."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            key, _, val = line.partition(":")
+            key = key.strip()
+            if key in ("model name", "cpu family", "model", "stepping") and key not in info:
+                info[key] = val.strip()
+            if len(info) == 4:
+                break
     except OSError:
         pass
-    return platform.processor() or "unknown"
+    name = info.get("model name") or platform.processor() or "unknown"
+    ids = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info)
+    return f"{name} ({ids}; {os.cpu_count()} threads visible)" if ids else name
 
 
 def cpu_baseline(batch, n_targets, n_single):
